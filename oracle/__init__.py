@@ -1,0 +1,19 @@
+"""FP64 CPU oracle for the block Vecchia log-likelihood.
+
+TEST INFRASTRUCTURE ONLY.  Nothing on the product path may import, call,
+link or execute anything in this package: only the test-suite, the smoke
+check and the benchmark's CPU-baseline leg use it.  It shares no code with
+the HIP library (no headers, kernels, helpers or tables); the only common
+dependency is the seeded input generator module ``workloads``.
+
+Contents (each function cites the passage of the paper it follows):
+  matern      - Matern covariance, eq. (maternkernel), plus the additive nugget
+  preprocess  - K-means (Section 2.1), random block order, block nearest
+                neighbours of each block centroid among earlier blocks
+  loglik      - Alg. 1 chain in numpy; exact GP, eq. (likeli); classic Vecchia;
+                trace-formula gradient; KL divergence, eq. (kl-gaussian-vecchia)
+  coracle     - the same Alg. 1 chain and gradient in plain C with OpenMP over
+                blocks (csrc/bv_oracle.c), for the larger workloads
+  simulate    - exact-GP and sequential-Vecchia data simulators
+  learned     - binned empirical variogram and an FP64 MLP forward/backward
+"""

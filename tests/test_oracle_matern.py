@@ -1,0 +1,60 @@
+"""Pins of the oracle's Matern covariance (eq. (maternkernel), Table 1)."""
+import os
+
+import numpy as np
+import pytest
+from scipy import special
+
+from oracle import matern
+from workloads import Theta
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "table1_beta.txt")
+
+
+def _bessel_form(x, nu):
+    # written independently of the oracle: 2^(1-nu)/Gamma(nu) x^nu K_nu(x)
+    return 2.0 ** (1 - nu) / special.gamma(nu) * x ** nu * special.kv(nu, x)
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_closed_forms_match_bessel(nu):
+    x = np.array([1e-3, 0.05, 0.3, 1.0, 2.5, 7.0, 20.0])
+    np.testing.assert_allclose(matern.rho(x, nu), _bessel_form(x, nu), rtol=1e-12)
+
+
+def test_rho_at_zero_is_one():
+    for nu in (0.5, 1.5, 2.5, 0.7):
+        assert matern.rho(np.array([0.0]), nu)[0] == pytest.approx(1.0, abs=0)
+
+
+def test_table1_pins_parametrisation():
+    """All nine printed beta give the same correlation at the effective range
+    only under x = h/beta (no sqrt(2 nu) factor).  The value is ~1/45."""
+    rows = np.loadtxt(GOLD, comments="#")
+    vals = [matern.effective_range_corr(b, nu, er) for er, nu, b in rows]
+    assert np.ptp(vals) < 1e-5
+    assert np.mean(vals) == pytest.approx(1.0 / 45.0, rel=2e-4)
+    # the sqrt(2 nu) h / beta reading spreads the nine values apart
+    alt = [float(_bessel_form(np.sqrt(2 * nu) * er / b, nu)) for er, nu, b in rows]
+    assert np.ptp(alt) > 1e-2
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.5, 2.5])
+def test_drho_dbeta_matches_fd(nu):
+    h = np.array([0.01, 0.05, 0.2, 0.6])
+    beta = 0.07
+    eps = 1e-7
+    fd = (matern.rho(h / (beta + eps), nu) - matern.rho(h / (beta - eps), nu)) / (2 * eps)
+    np.testing.assert_allclose(matern.drho_dbeta(h / beta, beta, nu), fd, rtol=1e-7)
+
+
+def test_nugget_only_on_same_index_and_anisotropy():
+    s = np.array([[0.1, 0.2, 0.00], [0.1, 0.2, 0.00], [0.3, 0.2, 0.01]])
+    th = Theta(2.0, 0.05, 0.1, 0.5, (1.0, 1.0, 0.2))
+    K = matern.cov(s, s, th, same=True)
+    # duplicate location, different index: no nugget
+    assert K[0, 1] == pytest.approx(2.0)
+    assert K[0, 0] == pytest.approx(2.1)
+    # per-axis range beta*aniso: dx = 0.2 over 0.05, dz = 0.01 over 0.01
+    x = np.sqrt((0.2 / 0.05) ** 2 + (0.01 / 0.01) ** 2)
+    assert K[0, 2] == pytest.approx(2.0 * np.exp(-x), rel=1e-14)

@@ -1,0 +1,65 @@
+"""Pins of the oracle's simulators, variogram and MLP."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import learned as LR, matern, simulate
+
+
+def test_sequential_vecchia_with_all_neighbours_is_exact_gp():
+    """With sim_m >= n-1 the sequential simulator is an exact factorisation:
+    y = T z with T T^T = K (linear in z, so probe with unit vectors)."""
+    n = 25
+    th = W.Theta(1.2, 0.2, 1e-3, 1.5)
+    s = W.rng(1).random((n, 2))
+    order = W.point_permutation(n, 1)
+    T = np.column_stack([simulate.sequential_vecchia(s, th, e, order, n) for e in np.eye(n)])
+    np.testing.assert_allclose(T @ T.T, matern.cov(s, s, th, same=True), rtol=1e-9, atol=1e-12)
+
+
+def test_exact_gp_factor():
+    n = 20
+    th = W.Theta(0.7, 0.1, 1e-4, 2.5)
+    s = W.rng(2).random((n, 2))
+    T = np.column_stack([simulate.exact_gp(s, th, e) for e in np.eye(n)])
+    np.testing.assert_allclose(T @ T.T, matern.cov(s, s, th, same=True), atol=1e-12)
+
+
+def test_variogram_hand_example():
+    # points on a line: distances 0.1, 0.2, 0.1 ; bins of width 0.5/32
+    s = np.array([[0.0, 0.0], [0.1, 0.0], [0.2, 0.0]])
+    y = np.array([1.0, 3.0, 0.0])
+    g, c = LR.variogram(s, y)
+    k1 = int(0.1 / 0.5 * 32)   # bin 6
+    k2 = int(0.2 / 0.5 * 32)   # bin 12
+    assert c[k1] == 2 and c[k2] == 1 and c.sum() == 3
+    assert g[k1] == pytest.approx(((1 - 3) ** 2 + (3 - 0) ** 2) / 4)
+    assert g[k2] == pytest.approx((1 - 0) ** 2 / 2)
+
+
+def test_mlp_backward_matches_fd():
+    p = LR.init_params(0, sizes=(6, 5, 4, 3))
+    g = W.rng(1)
+    X = g.standard_normal((7, 6))
+    T = g.standard_normal((7, 3))
+    out, cache = LR.forward(p, X)
+    loss, grads = LR.mse_backward(p, cache, out, T)
+    eps = 1e-6
+    for k, P in enumerate(p):
+        flat = P.reshape(-1)
+        for idx in range(0, flat.size, max(1, flat.size // 5)):
+            old = flat[idx]
+            flat[idx] = old + eps
+            lp = float(np.mean((LR.forward(p, X)[0] - T) ** 2))
+            flat[idx] = old - eps
+            lm = float(np.mean((LR.forward(p, X)[0] - T) ** 2))
+            flat[idx] = old
+            assert grads[k].reshape(-1)[idx] == pytest.approx((lp - lm) / (2 * eps), rel=1e-5, abs=1e-9)
+
+
+def test_adam_first_step_is_signed_lr():
+    # with bias correction, the first Adam step moves each weight by ~lr*sign(g)
+    p = [np.array([1.0, -2.0])]
+    gr = [np.array([0.3, -5.0])]
+    out, m, v = LR.adam_step(p, gr, [np.zeros(2)], [np.zeros(2)], 1, lr=0.01)
+    np.testing.assert_allclose(out[0], [1.0 - 0.01, -2.0 + 0.01], rtol=1e-6)
