@@ -1,0 +1,188 @@
+/* vecchia.h -- C ABI of the MI355X (gfx950) block Vecchia library.
+ *
+ * The library evaluates the block Vecchia approximation of a zero-mean
+ * Gaussian-process log-likelihood with a Matern covariance:
+ *
+ *   l(theta) = sum_i log p(y_{B_i} | y_{N_i})                 eq. (vecchia-vector)
+ *
+ * where B_1..B_bc is an ordered partition of the points into blocks
+ * (K-means clusters in random order, Section 2.1) and N_i holds the m_i
+ * points of earlier blocks nearest to the centroid of B_i (Alg. 1,
+ * preprocessing).  Each block term is computed by the chain of Alg. 1
+ * (Cholesky of the neighbour covariance, triangular solves, Schur update,
+ * Cholesky of the conditional covariance, log-determinant and quadratic
+ * form), fused into one workgroup per block.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers are DEVICE pointers unless the comment says "host".
+ *   - All work is enqueued on `stream` (a hipStream_t passed as void*;
+ *     NULL = the default stream).  Calls return after enqueueing; outputs are
+ *     valid once the stream has been synchronised.  Entry points that must
+ *     know a device-side count on the host (noted below) synchronise the
+ *     stream themselves.
+ *   - Locations are row-major n x d doubles, d in {1, 2, 3}.  Index arrays
+ *     are int32 (n < 2^31) unless typed otherwise.
+ *   - The caller owns every buffer, including the workspaces; the library
+ *     keeps no global state (apart from compiled kernels) and does not
+ *     allocate device memory.  Calls on different streams with different
+ *     workspaces may run concurrently.
+ *   - Return value: VECCHIA_OK or a negative vecchia_status for argument or
+ *     launch errors only.  Numerical outcomes (non-positive-definite
+ *     blocks, FP32 re-factorisations) are reported in-band through the
+ *     `counters` output.
+ */
+#ifndef VECCHIA_H
+#define VECCHIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  VECCHIA_OK = 0,
+  VECCHIA_EINVAL = -1,        /* bad argument (size, pointer, ordering) */
+  VECCHIA_ENOMEM = -2,        /* workspace or output capacity too small */
+  VECCHIA_EHIP = -3,          /* a HIP runtime call or launch failed */
+  VECCHIA_EUNSUPPORTED = -4   /* valid input outside what this build supports */
+} vecchia_status;
+
+typedef enum {
+  VECCHIA_FP64 = 0,       /* all arithmetic in FP64 */
+  VECCHIA_FP32_BULK = 1,  /* covariance, factorisations and solves in FP32; per-block
+                             log-det and quadratic form accumulated in FP64; cross-block
+                             sum in FP64; blocks whose FP32 pivots fall below the guard
+                             are re-factorised in FP64 */
+  VECCHIA_FP32_BULK_FORCE_REFACTOR = 2  /* test hook: FP32-bulk with every block flagged,
+                                           so every block is re-factorised in FP64 */
+} vecchia_precision;
+
+/* Matern parameters, eq. (maternkernel), plus a nugget and per-axis ranges:
+ *   C(s_i, s_j) = sigma2 * rho_nu(h / range) + nugget * [i == j],
+ *   h = || (s_i - s_j) / aniso ||  (componentwise division; aniso = {1,1,1}
+ *   is isotropic).  nu must be 0.5, 1.5 or 2.5 (closed forms
+ *   rho = e^-x, (1+x) e^-x, (1 + x + x^2/3) e^-x).  The nugget applies to
+ *   same-index pairs only (not to distinct points at distance zero). */
+typedef struct {
+  double sigma2;
+  double range;
+  double nugget;
+  double nu;
+  double aniso[3];
+} vecchia_theta;
+
+/* Version of this ABI (major*10000 + minor*100 + patch). */
+int vecchia_version(void);
+
+/* Text for a vecchia_status value (static storage). */
+const char* vecchia_status_string(int status);
+
+/* ---------------------------------------------------------------- blocks --
+ * Clustering g and block permutation zeta (Section 2.1; Alg. 1, preprocessing).
+ * Lloyd's K-means in metric-scaled coordinates x = s * metric_scale, started
+ * from the points init_idx[0..bc) and run until no assignment changes or
+ * max_iter iterations.  An empty cluster is re-seeded with the point farthest
+ * from its centroid.  Clusters are then ordered by block_perm (position i
+ * holds cluster block_perm[i]; empty clusters are dropped) and points inside
+ * a block keep ascending original index.
+ *   locs         n x d, original order
+ *   metric_scale host, d doubles (NULL = all ones)
+ *   init_idx     bc int64 distinct point indices
+ *   block_perm   bc int64, a permutation of 0..bc-1
+ *   perm         out, n int64: re-ordered position -> original index
+ *   block_ptr    out, bc+1 int32 CSR offsets of blocks in re-ordered points
+ *   bc_out       host out: number of non-empty blocks (<= bc)
+ *   iters_out    host out (may be NULL): Lloyd iterations run
+ *   workspace    >= vecchia_blocks_workspace_size(n, bc, d) bytes
+ * Synchronises `stream` (the block count is needed on the host). */
+size_t vecchia_blocks_workspace_size(int64_t n, int64_t bc, int32_t d);
+int vecchia_blocks(const double* locs, int64_t n, int32_t d, const double* metric_scale,
+                   const int64_t* init_idx, const int64_t* block_perm, int64_t bc, int32_t max_iter,
+                   int64_t* perm, int32_t* block_ptr, int64_t* bc_out, int32_t* iters_out,
+                   void* workspace, size_t ws_bytes, void* stream);
+
+/* Row gather dst[i, :] = src[perm[i], :] for an n x d double array (locations
+ * or, with d = 1, data) -- the re-ordering of points into block order.
+ * Asynchronous. */
+int vecchia_permute(const double* src, int64_t n, int32_t d, const int64_t* perm, double* dst, void* stream);
+
+/* ------------------------------------------------------------- neighbors --
+ * Conditioning sets (Alg. 1, nearest neighbours; Section 2.2): for block i,
+ * the m_i = min(m, block_ptr[i]) points of blocks 0..i-1 nearest to the
+ * block centroid, sorted by (squared distance, index).  The centroid is the
+ * mean of the block's metric-scaled points summed in order; squared
+ * distances are FP64 sums (c_k - s_k*w_k)^2, k ascending, without fused
+ * multiply-add, so results are reproducible bit for bit.  m = -1 selects
+ * every earlier point (ascending index).
+ *   locs_perm    n x d, block order (locs[perm])
+ *   block_ptr    bc+1 int32
+ *   nbr_ptr      out, bc+1 int32 CSR offsets (written by the call)
+ *   nbr_idx      out, capacity nbr_cap int32 indices into the re-ordered points
+ *   workspace    >= vecchia_neighbors_workspace_size(n, bc, d, m) bytes
+ * Returns VECCHIA_ENOMEM if sum_i m_i exceeds nbr_cap.  Synchronises `stream`. */
+size_t vecchia_neighbors_workspace_size(int64_t n, int64_t bc, int32_t d, int32_t m);
+int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const double* metric_scale,
+                      const int32_t* block_ptr, int64_t bc, int32_t m,
+                      int32_t* nbr_ptr, int32_t* nbr_idx, int64_t nbr_cap,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ plan --
+ * Launch schedule for one (block_ptr, nbr_ptr) pair: blocks are grouped into
+ * size classes by p_i = m_i + l_i so that each class runs the register-tile
+ * configuration that fits it.  Build once per data set, reuse for every
+ * likelihood evaluation.  The struct is host memory owned by the caller; its
+ * device arrays live in the caller's workspace, which must stay allocated
+ * while the plan is used.  Synchronises `stream`.
+ *   max_theta    largest ntheta that later calls will pass
+ *   workspace    >= vecchia_plan_workspace_size(bc, max_theta) bytes
+ * Returns VECCHIA_EUNSUPPORTED if some block has m_i + l_i above
+ * VECCHIA_MAX_JOINT (use smaller m, or smaller blocks). */
+#define VECCHIA_MAX_BUCKETS 24
+#define VECCHIA_MAX_JOINT 176
+typedef struct {
+  int64_t n, bc;
+  int32_t max_theta;
+  int32_t nbuckets;
+  int32_t pmax, lmax, mmax;
+  int32_t bucket_cfg[VECCHIA_MAX_BUCKETS];     /* kernel configuration of each class */
+  int64_t bucket_off[VECCHIA_MAX_BUCKETS + 1]; /* class ranges in the schedule array */
+  int64_t lsum;                                /* sum of l_i (= n when blocks cover all points) */
+  double flops_la;                             /* sum_i (p_i^3/3 + p_i^2): algorithmic LA flops */
+  double cov_entries;                          /* sum_i p_i (p_i + 1) / 2 */
+  void* ws;
+  size_t ws_bytes;
+  size_t off_sched, off_partial, off_flag, off_list, off_count, off_chunk, off_grad;
+} vecchia_plan;
+
+size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
+int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, const int32_t* nbr_ptr,
+                      int64_t n, int64_t bc, int32_t max_theta,
+                      void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- loglik --
+ * Block Vecchia log-likelihood (Alg. 1) for ntheta parameter vectors.
+ *   plan         from vecchia_plan_init on the same block_ptr / nbr_ptr
+ *   locs_perm    n x d, block order;  y_perm: n doubles, block order
+ *   nbr_idx      neighbour indices (every index of block i < block_ptr[i])
+ *   theta        host, ntheta values (ntheta <= plan->max_theta)
+ *   precision    vecchia_precision
+ *   loglik       out, ntheta doubles
+ *   counters     out or NULL, 2*ntheta int32: [t*2+0] blocks re-factorised in
+ *                FP64 by the FP32 guard, [t*2+1] blocks that were not positive
+ *                definite even in FP64 (then loglik[t] is NaN)
+ *   partial      out or NULL, ntheta*bc doubles: per-block terms l_i,
+ *                [t*bc + i]
+ * The FP32 guard flags a block when a pivot d_k (the diagonal before the
+ * square root, in either Cholesky) is not finite or falls below
+ * max(nugget/2, p_i * 2^-23 * (sigma2 + nugget)). */
+int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                   const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                   const vecchia_theta* theta, int32_t ntheta, int32_t precision,
+                   double* loglik, int32_t* counters, double* partial, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VECCHIA_H */

@@ -35,6 +35,10 @@ def lib():
             f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+        f = L.bvo_simulate
+        f.restype = ctypes.c_int64
+        f.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         _lib = L
     return _lib
 
@@ -94,3 +98,21 @@ def grad(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta, nthreads: int = 
     for row in g:
         acc = acc + row
     return acc
+
+
+def simulate(locs_perm, block_ptr, nbr_ptr, nbr_idx, theta, z):
+    """Draw y (block order) from the block Vecchia density, blocks in order.
+    With unit blocks and nearest-earlier-point neighbours this is the
+    sequential Vecchia simulator."""
+    locs = _c(locs_perm, np.float64)
+    bp = _c(block_ptr, np.int64)
+    npt = _c(nbr_ptr, np.int64)
+    ni = _c(nbr_idx, np.int64) if len(nbr_idx) else np.zeros(1, np.int64)
+    zz = _c(z, np.float64)
+    y = np.zeros(locs.shape[0])
+    bad = lib().bvo_simulate(locs.ctypes.data, locs.shape[0], locs.shape[1], bp.ctypes.data, bp.size - 1,
+                             npt.ctypes.data, ni.ctypes.data, _theta7(theta).ctypes.data, zz.ctypes.data,
+                             y.ctypes.data)
+    if bad:
+        raise ValueError(f"{bad} blocks not positive definite in simulation")
+    return y

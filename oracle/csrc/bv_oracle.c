@@ -254,3 +254,61 @@ int64_t bvo_grad(const double* locs, const double* y, int64_t n, int32_t d,
   }
   return bad;
 }
+
+/* Sequential simulation from the block Vecchia density (eq. (vecchia-vector)),
+ * blocks in order: y_B = mu + chol(S) z_B with mu = K_BN K_NN^-1 y_N and
+ * S = K_BB - K_BN K_NN^-1 K_NB.  With blocks of size one and N(i) the nearest
+ * earlier points this is the sequential (classic) Vecchia simulator.  Sequential
+ * over blocks: each block reads values drawn for earlier blocks. */
+int64_t bvo_simulate(const double* locs, int64_t n, int32_t d, const int64_t* block_ptr, int64_t bc,
+                     const int64_t* nbr_ptr, const int64_t* nbr_idx, const double* theta7, const double* z,
+                     double* y) {
+  (void)n;
+  bvo_theta th = {theta7[0], theta7[1], theta7[2], theta7[3], {theta7[4], theta7[5], theta7[6]}};
+  int lmax, mmax;
+  max_block(block_ptr, bc, nbr_ptr, &lmax, &mmax);
+  double* work = (double*)malloc(sizeof(double) * ((size_t)lmax * lmax + (size_t)mmax * mmax +
+                                                   (size_t)mmax * lmax + mmax + 2 * lmax + 8));
+  int64_t bad = 0;
+  for (int64_t i = 0; i < bc; ++i) {
+    int64_t b0 = block_ptr[i], b1 = block_ptr[i + 1];
+    int l = (int)(b1 - b0), m = (int)(nbr_ptr[i + 1] - nbr_ptr[i]);
+    const int64_t* nn = nbr_idx + nbr_ptr[i];
+    double* S = work;              /* l x l */
+    double* Kn = S + l * l;        /* m x m */
+    double* Kc = Kn + m * m;       /* m x l */
+    double* yn = Kc + m * l;       /* m */
+    double* mu = yn + m;           /* l */
+    for (int a = 0; a < l; ++a)
+      for (int b = 0; b < l; ++b) S[a * l + b] = cov(locs + (b0 + a) * d, locs + (b0 + b) * d, d, &th, a == b);
+    for (int a = 0; a < l; ++a) mu[a] = 0.0;
+    if (m > 0) {
+      for (int a = 0; a < m; ++a) {
+        for (int b = 0; b < m; ++b) Kn[a * m + b] = cov(locs + nn[a] * d, locs + nn[b] * d, d, &th, a == b);
+        for (int b = 0; b < l; ++b) Kc[a * l + b] = cov(locs + nn[a] * d, locs + (b0 + b) * d, d, &th, 0);
+        yn[a] = y[nn[a]];
+      }
+      if (potrf(Kn, m)) { bad++; continue; }
+      trsm_lower(Kn, m, Kc, l);
+      trsm_lower(Kn, m, yn, 1);
+      for (int a = 0; a < l; ++a) {
+        double s = 0.0;
+        for (int k = 0; k < m; ++k) s += Kc[k * l + a] * yn[k];
+        mu[a] = s;
+        for (int b = 0; b < l; ++b) {
+          double t = 0.0;
+          for (int k = 0; k < m; ++k) t += Kc[k * l + a] * Kc[k * l + b];
+          S[a * l + b] -= t;
+        }
+      }
+    }
+    if (potrf(S, l)) { bad++; continue; }
+    for (int a = 0; a < l; ++a) {
+      double s = mu[a];
+      for (int k = 0; k <= a; ++k) s += S[a * l + k] * z[b0 + k];
+      y[b0 + a] = s;
+    }
+  }
+  free(work);
+  return bad;
+}

@@ -1,0 +1,80 @@
+"""ctypes binding of libvecchia.so (include/vecchia.h).  Argument marshalling
+only: every step of the computation runs in the library's HIP kernels.
+Importing this module raises if the built library is missing."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libvecchia.so")
+
+MAX_BUCKETS = 24
+MAX_JOINT = 176
+
+OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+FP64, FP32_BULK = 0, 1
+
+
+class Theta(ctypes.Structure):
+    _fields_ = [("sigma2", ctypes.c_double), ("range", ctypes.c_double), ("nugget", ctypes.c_double),
+                ("nu", ctypes.c_double), ("aniso", ctypes.c_double * 3)]
+
+
+class Plan(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("bc", ctypes.c_int64), ("max_theta", ctypes.c_int32),
+                ("nbuckets", ctypes.c_int32), ("pmax", ctypes.c_int32), ("lmax", ctypes.c_int32),
+                ("mmax", ctypes.c_int32), ("bucket_cfg", ctypes.c_int32 * MAX_BUCKETS),
+                ("bucket_off", ctypes.c_int64 * (MAX_BUCKETS + 1)), ("lsum", ctypes.c_int64),
+                ("flops_la", ctypes.c_double), ("cov_entries", ctypes.c_double),
+                ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
+                ("off_sched", ctypes.c_size_t), ("off_partial", ctypes.c_size_t), ("off_flag", ctypes.c_size_t),
+                ("off_list", ctypes.c_size_t), ("off_count", ctypes.c_size_t), ("off_chunk", ctypes.c_size_t),
+                ("off_grad", ctypes.c_size_t)]
+
+
+class VecchiaError(RuntimeError):
+    pass
+
+
+P = ctypes.c_void_p
+I32, I64, SZ, D = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+
+# name -> (restype, argtypes); the list mirrors include/vecchia.h
+SIGNATURES = {
+    "vecchia_version": (ctypes.c_int, []),
+    "vecchia_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "vecchia_blocks_workspace_size": (SZ, [I64, I64, I32]),
+    "vecchia_blocks": (ctypes.c_int, [P, I64, I32, P, P, P, I64, I32, P, P, P, P, P, SZ, P]),
+    "vecchia_neighbors_workspace_size": (SZ, [I64, I64, I32, I32]),
+    "vecchia_neighbors": (ctypes.c_int, [P, I64, I32, P, P, I64, I32, P, P, I64, P, SZ, P]),
+    "vecchia_plan_workspace_size": (SZ, [I64, I32]),
+    "vecchia_plan_init": (ctypes.c_int, [P, P, P, I64, I64, I32, P, SZ, P]),
+    "vecchia_loglik": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P]),
+    "vecchia_permute": (ctypes.c_int, [P, I64, I32, P, P, P]),
+}
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise VecchiaError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run `python -m paper_2410_04477_amd.build`)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name, None)
+            if f is None:
+                continue
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(status: int, what: str) -> None:
+    if status != OK:
+        msg = lib().vecchia_status_string(status).decode()
+        raise VecchiaError(f"{what} failed: {msg} ({status})")

@@ -1,0 +1,150 @@
+"""Python face of the block Vecchia library.  PyTorch supplies device memory
+and the current HIP stream; all computation happens in libvecchia.so."""
+from __future__ import annotations
+
+import ctypes
+from typing import Iterable, Optional, Sequence
+
+import torch
+
+from . import _lib as L
+
+PRECISIONS = {"fp64": L.FP64, "fp32": L.FP32_BULK, "fp32_bulk": L.FP32_BULK, "fp32_force_refactor": 2}
+
+
+def _stream(device: Optional[torch.device] = None) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev_check(*ts: torch.Tensor) -> torch.device:
+    dev = None
+    for t in ts:
+        if t is None:
+            continue
+        if not t.is_cuda:
+            raise ValueError("tensors must live on the HIP device")
+        if not t.is_contiguous():
+            raise ValueError("tensors must be contiguous")
+        dev = t.device if dev is None else dev
+    return dev
+
+
+def make_theta(th) -> L.Theta:
+    """Accepts an object with sigma2/beta(or range)/nugget/nu/aniso, or a tuple
+    (sigma2, range, nugget, nu[, aniso])."""
+    if isinstance(th, L.Theta):
+        return th
+    if isinstance(th, (tuple, list)):
+        s2, rg, nug, nu = th[:4]
+        an = th[4] if len(th) > 4 else (1.0, 1.0, 1.0)
+    else:
+        s2, nug, nu = th.sigma2, th.nugget, th.nu
+        rg = getattr(th, "range", None) or th.beta
+        an = getattr(th, "aniso", (1.0, 1.0, 1.0))
+    an = tuple(an) + (1.0,) * (3 - len(an))
+    return L.Theta(float(s2), float(rg), float(nug), float(nu), (ctypes.c_double * 3)(*an))
+
+
+def permute_rows(src: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
+    """dst[i] = src[perm[i]] (rows), done by the library's gather kernel."""
+    _dev_check(src, perm)
+    d = 1 if src.dim() == 1 else src.shape[1]
+    dst = torch.empty_like(src)
+    L.check(L.lib().vecchia_permute(_p(src), src.shape[0], d, _p(perm), _p(dst), _stream(src.device)),
+            "vecchia_permute")
+    return dst
+
+
+def blocks(locs: torch.Tensor, bc: int, init_idx: torch.Tensor, block_perm: torch.Tensor,
+           metric_scale: Optional[Sequence[float]] = None, max_iter: int = 30):
+    """K-means blocks in random order.  Returns (perm int64[n], block_ptr int32[bc'+1], iters)."""
+    _dev_check(locs, init_idx, block_perm)
+    n, d = locs.shape
+    lib = L.lib()
+    ws = torch.empty(int(lib.vecchia_blocks_workspace_size(n, bc, d)), dtype=torch.uint8, device=locs.device)
+    perm = torch.empty(n, dtype=torch.int64, device=locs.device)
+    bp = torch.empty(bc + 1, dtype=torch.int32, device=locs.device)
+    bc_out = ctypes.c_int64(0)
+    iters = ctypes.c_int32(0)
+    ms = (ctypes.c_double * d)(*metric_scale) if metric_scale is not None else None
+    L.check(lib.vecchia_blocks(_p(locs), n, d, ms, _p(init_idx), _p(block_perm), bc, max_iter, _p(perm), _p(bp),
+                               ctypes.byref(bc_out), ctypes.byref(iters), _p(ws), ws.numel(),
+                               _stream(locs.device)), "vecchia_blocks")
+    return perm, bp[: bc_out.value + 1].clone(), iters.value
+
+
+def neighbors(locs_perm: torch.Tensor, block_ptr: torch.Tensor, m: int,
+              metric_scale: Optional[Sequence[float]] = None):
+    """Nearest earlier points of each block centroid.  Returns (nbr_ptr int32, nbr_idx int32)."""
+    _dev_check(locs_perm, block_ptr)
+    n, d = locs_perm.shape
+    bc = block_ptr.numel() - 1
+    lib = L.lib()
+    cap = n * (n + 1) // 2 if m < 0 else bc * m
+    cap = max(1, min(cap, 2**31 - 1))
+    ws = torch.empty(int(lib.vecchia_neighbors_workspace_size(n, bc, d, m)), dtype=torch.uint8,
+                     device=locs_perm.device)
+    nptr = torch.empty(bc + 1, dtype=torch.int32, device=locs_perm.device)
+    nidx = torch.empty(cap, dtype=torch.int32, device=locs_perm.device)
+    ms = (ctypes.c_double * d)(*metric_scale) if metric_scale is not None else None
+    L.check(lib.vecchia_neighbors(_p(locs_perm), n, d, ms, _p(block_ptr), bc, m, _p(nptr), _p(nidx), cap,
+                                  _p(ws), ws.numel(), _stream(locs_perm.device)), "vecchia_neighbors")
+    total = int(nptr[-1].item())
+    return nptr, nidx[:total].clone()
+
+
+class Plan:
+    """Launch schedule for one block / neighbour structure (vecchia_plan_init)."""
+
+    def __init__(self, block_ptr: torch.Tensor, nbr_ptr: torch.Tensor, n: int, max_theta: int = 1):
+        _dev_check(block_ptr, nbr_ptr)
+        if block_ptr.dtype != torch.int32 or nbr_ptr.dtype != torch.int32:
+            raise ValueError("block_ptr / nbr_ptr must be int32")
+        lib = L.lib()
+        bc = block_ptr.numel() - 1
+        self.ws = torch.empty(int(lib.vecchia_plan_workspace_size(bc, max_theta)), dtype=torch.uint8,
+                              device=block_ptr.device)
+        self.c = L.Plan()
+        L.check(lib.vecchia_plan_init(ctypes.byref(self.c), _p(block_ptr), _p(nbr_ptr), n, bc, max_theta,
+                                      _p(self.ws), self.ws.numel(), _stream(block_ptr.device)),
+                "vecchia_plan_init")
+        self.block_ptr, self.nbr_ptr = block_ptr, nbr_ptr
+
+    @property
+    def bc(self) -> int:
+        return int(self.c.bc)
+
+    @property
+    def flops_la(self) -> float:
+        return float(self.c.flops_la)
+
+    @property
+    def cov_entries(self) -> float:
+        return float(self.c.cov_entries)
+
+    def buckets(self):
+        return [(int(self.c.bucket_cfg[q]), int(self.c.bucket_off[q + 1] - self.c.bucket_off[q]))
+                for q in range(self.c.nbuckets)]
+
+
+def loglik(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_idx: torch.Tensor,
+           thetas: Iterable, precision: str = "fp64", want_partial: bool = False):
+    """Block Vecchia log-likelihood for each theta.  Returns (loglik[ntheta] f64,
+    counters[ntheta, 2] i32, partial[ntheta, bc] or None) as device tensors."""
+    _dev_check(locs_perm, y_perm, nbr_idx)
+    th = [make_theta(t) for t in thetas]
+    nt = len(th)
+    arr = (L.Theta * nt)(*th)
+    dev = locs_perm.device
+    out = torch.empty(nt, dtype=torch.float64, device=dev)
+    cnt = torch.empty((nt, 2), dtype=torch.int32, device=dev)
+    part = torch.empty((nt, plan.bc), dtype=torch.float64, device=dev) if want_partial else None
+    d = 1 if locs_perm.dim() == 1 else locs_perm.shape[1]
+    L.check(L.lib().vecchia_loglik(ctypes.byref(plan.c), _p(locs_perm), _p(y_perm), d, _p(plan.block_ptr),
+                                   _p(plan.nbr_ptr), _p(nbr_idx), arr, nt, PRECISIONS[precision], _p(out), _p(cnt),
+                                   _p(part), _stream(dev)), "vecchia_loglik")
+    return out, cnt, part

@@ -1,0 +1,238 @@
+// C ABI of the block Vecchia library: argument checking, workspace layout,
+// launch orchestration.  Every numerical step runs in the HIP kernels.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "internal.hpp"
+
+using namespace bv;
+
+#define VCHECK_HIP(x)                        \
+  do {                                       \
+    hipError_t e_ = (x);                     \
+    if (e_ != hipSuccess) return VECCHIA_EHIP; \
+  } while (0)
+
+static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+extern "C" int vecchia_version(void) { return 10000; }
+
+extern "C" const char* vecchia_status_string(int status) {
+  switch (status) {
+    case VECCHIA_OK: return "ok";
+    case VECCHIA_EINVAL: return "invalid argument";
+    case VECCHIA_ENOMEM: return "workspace or output capacity too small";
+    case VECCHIA_EHIP: return "HIP runtime error";
+    case VECCHIA_EUNSUPPORTED: return "unsupported input";
+    default: return "unknown status";
+  }
+}
+
+// ---------------------------------------------------------------- plan ----
+
+namespace {
+struct PlanLayout {
+  size_t sched, partial, flag, list, count, chunk, grad, scratch, total;
+};
+
+PlanLayout plan_layout(int64_t bc, int32_t max_theta) {
+  PlanLayout L;
+  size_t o = 0;
+  const size_t nb = (size_t)bc, nt = (size_t)max_theta;
+  L.sched = o;   o = align256(o + sizeof(int) * nb);
+  L.partial = o; o = align256(o + sizeof(double) * nb * nt);
+  L.flag = o;    o = align256(o + sizeof(int) * nb * nt);
+  L.list = o;    o = align256(o + sizeof(int) * nb * nt);
+  L.count = o;   o = align256(o + sizeof(int) * 64);
+  L.chunk = o;   o = align256(o + sizeof(double) * 64);
+  L.grad = o;    o = align256(o + sizeof(double) * nb * nt * 3);
+  L.scratch = o; o = align256(o + sizeof(int) * (nb + 256) + sizeof(unsigned long long) * 8);
+  L.total = o;
+  return L;
+}
+
+bool theta_to_dev(const vecchia_theta& t, int d, ThetaDev& o) {
+  if (!(t.sigma2 > 0) || !(t.range > 0) || !(t.nugget >= 0) || !isfinite(t.sigma2) || !isfinite(t.range) ||
+      !isfinite(t.nugget))
+    return false;
+  if (t.nu == 0.5) o.nu_code = 0;
+  else if (t.nu == 1.5) o.nu_code = 1;
+  else if (t.nu == 2.5) o.nu_code = 2;
+  else return false;
+  o.sigma2 = t.sigma2;
+  o.nugget = t.nugget;
+  o.inv_range = 1.0 / t.range;
+  for (int k = 0; k < 3; ++k) {
+    if (k < d) {
+      if (!(t.aniso[k] > 0)) return false;
+      o.inv_scale[k] = 1.0 / (t.range * t.aniso[k]);
+    } else {
+      o.inv_scale[k] = 0.0;
+    }
+  }
+  o.pad_ = 0;
+  return true;
+}
+
+template <typename P> P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(base) + off); }
+}  // namespace
+
+extern "C" size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta) {
+  if (bc <= 0 || max_theta <= 0) return 0;
+  return plan_layout(bc, max_theta).total;
+}
+
+extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, const int32_t* nbr_ptr, int64_t n,
+                                 int64_t bc, int32_t max_theta, void* workspace, size_t ws_bytes, void* stream) {
+  if (!plan || !block_ptr || !nbr_ptr || !workspace || n <= 0 || bc <= 0 || bc > n || max_theta <= 0 ||
+      n >= (int64_t)1 << 31 || (int64_t)bc * max_theta >= (int64_t)1 << 31)
+    return VECCHIA_EINVAL;
+  const PlanLayout L = plan_layout(bc, max_theta);
+  if (ws_bytes < L.total) return VECCHIA_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  memset(plan, 0, sizeof(*plan));
+  int* cfg_of = at<int>(workspace, L.scratch);
+  int* counts = at<int>(workspace, L.count);            // [0..32) counts, [32..64) cursors/offsets
+  unsigned long long* stats = at<unsigned long long>(workspace, L.chunk);
+  int* maxes = at<int>(workspace, L.chunk + 128);
+  VCHECK_HIP(launch_fill_int(counts, 64, 0, s));
+  VCHECK_HIP(launch_fill_int(maxes, 16, 0, s));
+  VCHECK_HIP(launch_fill_int(reinterpret_cast<int*>(stats), 16, 0, s));
+  VCHECK_HIP(launch_classify(block_ptr, nbr_ptr, (int)bc, cfg_of, counts, stats, maxes, s));
+  int hcounts[32];
+  int hmax[4];
+  unsigned long long hstats[4];
+  VCHECK_HIP(hipMemcpyAsync(hcounts, counts, sizeof(hcounts), hipMemcpyDeviceToHost, s));
+  VCHECK_HIP(hipMemcpyAsync(hmax, maxes, sizeof(hmax), hipMemcpyDeviceToHost, s));
+  VCHECK_HIP(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
+  VCHECK_HIP(hipStreamSynchronize(s));
+  if (hmax[3] > 0) {
+    // a block with no points, or with m_i + l_i above the largest tile configuration
+    return hmax[0] > VECCHIA_MAX_JOINT ? VECCHIA_EUNSUPPORTED : VECCHIA_EINVAL;
+  }
+  int hoff[32];
+  int acc = 0, nb = 0;
+  for (int c = 0; c < kNumCfgs; ++c) {
+    hoff[c] = acc;
+    if (hcounts[c] > 0) {
+      plan->bucket_cfg[nb] = c;
+      plan->bucket_off[nb] = acc;
+      ++nb;
+    }
+    acc += hcounts[c];
+  }
+  plan->bucket_off[nb] = acc;
+  plan->nbuckets = nb;
+  VCHECK_HIP(hipMemcpyAsync(counts + 32, hoff, sizeof(int) * kNumCfgs, hipMemcpyHostToDevice, s));
+  VCHECK_HIP(launch_fill_int(counts, 32, 0, s));
+  VCHECK_HIP(launch_scatter(cfg_of, (int)bc, counts + 32, counts, at<int>(workspace, L.sched), s));
+  VCHECK_HIP(hipStreamSynchronize(s));
+  plan->n = n;
+  plan->bc = bc;
+  plan->max_theta = max_theta;
+  plan->pmax = hmax[0];
+  plan->lmax = hmax[1];
+  plan->mmax = hmax[2];
+  plan->flops_la = (double)hstats[0] / 3.0 + (double)hstats[1];
+  plan->cov_entries = (double)hstats[2];
+  plan->lsum = (int64_t)hstats[3];
+  plan->ws = workspace;
+  plan->ws_bytes = ws_bytes;
+  plan->off_sched = L.sched;
+  plan->off_partial = L.partial;
+  plan->off_flag = L.flag;
+  plan->off_list = L.list;
+  plan->off_count = L.count;
+  plan->off_chunk = L.chunk;
+  plan->off_grad = L.grad;
+  return VECCHIA_OK;
+}
+
+// -------------------------------------------------------------- loglik ----
+
+static int check_common(const vecchia_plan* plan, const double* locs, const double* y, int32_t d,
+                        const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                        const vecchia_theta* theta, int32_t ntheta, int32_t precision) {
+  if (!plan || !plan->ws || !locs || !y || !block_ptr || !nbr_ptr || !nbr_idx || !theta) return VECCHIA_EINVAL;
+  if (d < 1 || d > 3 || ntheta < 1 || ntheta > plan->max_theta) return VECCHIA_EINVAL;
+  if (precision != VECCHIA_FP64 && precision != VECCHIA_FP32_BULK && precision != VECCHIA_FP32_BULK_FORCE_REFACTOR)
+    return VECCHIA_EINVAL;
+  for (int t = 0; t < ntheta; ++t) {
+    ThetaDev td;
+    if (!theta_to_dev(theta[t], d, td)) return (theta[t].nu == 0.5 || theta[t].nu == 1.5 || theta[t].nu == 2.5)
+                                                   ? VECCHIA_EINVAL
+                                                   : VECCHIA_EUNSUPPORTED;
+  }
+  return VECCHIA_OK;
+}
+
+extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                              const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                              const vecchia_theta* theta, int32_t ntheta, int32_t precision, double* loglik,
+                              int32_t* counters, double* partial, void* stream) {
+  int st = check_common(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision);
+  if (st) return st;
+  if (!loglik) return VECCHIA_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int bc = (int)plan->bc;
+  void* ws = plan->ws;
+  const bool fp32 = precision != VECCHIA_FP64;
+  const int* sched = at<int>(ws, plan->off_sched);
+  double* part = at<double>(ws, plan->off_partial);
+  int* flag = at<int>(ws, plan->off_flag);
+  int* list = at<int>(ws, plan->off_list);
+  int* count = at<int>(ws, plan->off_count);
+
+  for (int t0 = 0; t0 < ntheta; t0 += kMaxThetaPerLaunch) {
+    const int nt = ntheta - t0 < kMaxThetaPerLaunch ? ntheta - t0 : kMaxThetaPerLaunch;
+    ThetaPack thp;
+    memset(&thp, 0, sizeof(thp));
+    for (int t = 0; t < nt; ++t) theta_to_dev(theta[t0 + t], d, thp.t[t]);
+    FwdArgs a;
+    memset(&a, 0, sizeof(a));
+    a.locs = locs_perm;
+    a.y = y_perm;
+    a.block_ptr = block_ptr;
+    a.nbr_ptr = nbr_ptr;
+    a.nbr_idx = nbr_idx;
+    a.ntheta = nt;
+    a.bc = bc;
+    a.d = d;
+    a.fp32_guard = precision == VECCHIA_FP32_BULK_FORCE_REFACTOR ? 2 : (fp32 ? 1 : 0);
+    a.partial = part;
+    a.flag = flag;
+    for (int q = 0; q < plan->nbuckets; ++q) {
+      const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+      a.sched = sched + plan->bucket_off[q];
+      a.nsched = ns;
+      VCHECK_HIP(launch_forward(plan->bucket_cfg[q], fp32, a, thp, ns * nt, s));
+    }
+    if (fp32) {
+      // FP32 guard: compact flagged (theta, block) pairs per size class, re-run them in FP64
+      VCHECK_HIP(launch_fill_int(count, plan->nbuckets, 0, s));
+      for (int q = 0; q < plan->nbuckets; ++q) {
+        const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+        VCHECK_HIP(launch_compact_flagged(sched + plan->bucket_off[q], ns, nt, bc, flag,
+                                          list + plan->bucket_off[q] * nt, count + q, s));
+      }
+      FwdArgs r = a;
+      r.fp32_guard = 0;
+      r.flag_or = 4;
+      for (int q = 0; q < plan->nbuckets; ++q) {
+        const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+        r.list = list + plan->bucket_off[q] * nt;
+        r.list_count = count + q;
+        const int cap = ns * nt;
+        VCHECK_HIP(launch_forward(plan->bucket_cfg[q], false, r, thp, cap < 256 ? cap : 256, s));
+      }
+    }
+    VCHECK_HIP(launch_reduce_partials(part, flag, bc, nt, fp32 ? 0 : 1, loglik + t0,
+                                      counters ? counters + 2 * t0 : nullptr, s));
+    if (partial)
+      VCHECK_HIP(hipMemcpyAsync(partial + (size_t)t0 * bc, part, sizeof(double) * (size_t)nt * bc,
+                                hipMemcpyDeviceToDevice, s));
+  }
+  return VECCHIA_OK;
+}

@@ -1,0 +1,39 @@
+// Internal interfaces between the C ABI layer and the kernels.
+#pragma once
+
+#include "common.hpp"
+
+namespace bv {
+
+struct FwdArgs {
+  const double* locs;
+  const double* y;
+  const int* block_ptr;
+  const int* nbr_ptr;
+  const int* nbr_idx;
+  const int* sched;      // block ids of this size class (schedule mode)
+  const int* list;       // (theta, block) pairs, packed theta * bc + block (list mode)
+  const int* list_count; // device count of list entries (list mode)
+  int nsched;            // schedule mode: blocks in this class
+  int ntheta;
+  int bc;
+  int d;
+  int fp32_guard;        // 1: flag blocks whose FP32 pivots fall below the guard
+  int flag_or;           // OR-ed into every flag written (4 marks an FP64 re-factorisation)
+  double* partial;       // [theta * bc + block]
+  int* flag;             // [theta * bc + block]: 1 guard tripped, 2 non-positive pivot, 4 re-run in FP64
+};
+
+hipError_t launch_forward(int cfg, bool fp32, const FwdArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+
+hipError_t launch_classify(const int* block_ptr, const int* nbr_ptr, int bc, int* cfg_of, int* counts,
+                           unsigned long long* stats, int* maxes, hipStream_t s);
+hipError_t launch_scatter(const int* cfg_of, int bc, const int* cfg_off, int* cursor, int* sched, hipStream_t s);
+hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
+hipError_t launch_compact_flagged(const int* sched, int nsched, int ntheta, int bc, const int* flag, int* list,
+                                  int* count, hipStream_t s);
+hipError_t launch_reduce_partials(const double* partial, const int* flag, int bc, int ntheta, int fp64_only,
+                                  double* out, int* counters, hipStream_t s);
+hipError_t launch_reduce_vec(const double* vec, int bc, int k, int ntheta, double* out, hipStream_t s);
+
+}  // namespace bv

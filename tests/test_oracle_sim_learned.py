@@ -63,3 +63,19 @@ def test_adam_first_step_is_signed_lr():
     gr = [np.array([0.3, -5.0])]
     out, m, v = LR.adam_step(p, gr, [np.zeros(2)], [np.zeros(2)], 1, lr=0.01)
     np.testing.assert_allclose(out[0], [1.0 - 0.01, -2.0 + 0.01], rtol=1e-6)
+
+
+def test_c_block_simulator_matches_sequential_vecchia():
+    """Unit blocks + nearest earlier points: the C block simulator is the
+    sequential Vecchia simulator of the numpy oracle (same draws)."""
+    from oracle import coracle
+    from oracle.preprocess import point_neighbors
+    n, m = 60, 8
+    th = W.Theta(1.1, 0.15, 1e-3, 2.5)
+    s = W.rng(3).random((n, 2))
+    order = W.point_permutation(n, 3)
+    z = W.standard_normal(n, 4)
+    ref = simulate.sequential_vecchia(s, th, z, order, m)
+    ptr, idx = point_neighbors(s[order], m)
+    ys = coracle.simulate(s[order], np.arange(n + 1), ptr, idx, th, z)
+    np.testing.assert_allclose(ys, ref[order], rtol=1e-10, atol=1e-12)
