@@ -1,0 +1,271 @@
+#!/usr/bin/env python
+"""Block Vecchia benchmark on one MI355X.
+
+A step is one evaluation of the block Vecchia log-likelihood together with
+its adjoint gradient w.r.t. (sigma2, range, nugget), in the FP32-bulk
+precision (FP64 accumulation, FP64 re-factorisation of guard-flagged blocks),
+on the 1e6-point 3-D workload: x, y uniform in [0,1], z uniform in [0,0.2],
+Matern nu = 2.5, sigma2 = 1, ranges 0.05/0.05/0.01, nugget 1e-3, y drawn by the
+sequential Vecchia simulator with 150 neighbours, 50,000 K-means blocks in
+random order, 120 neighbours per block.  Inputs are resident in HBM before
+the timed region; preprocessing (simulation, K-means, neighbours, plan) is
+untimed.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--gpus 1]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "block-Vecchia loglik evals/s and points/s at n=1e6, FP32 vs FP64 @1e-4 rel err"
+FP32_VECTOR_PEAK = 157.3e12   # MI355X published FP32 vector FLOP/s
+FP64_VECTOR_PEAK = 78.6e12
+
+
+def log(msg: str) -> None:
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for f in ("bv_adjoint.hip", "bv_forward.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2410_04477_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def step_flops(p, m, l):
+    """Algorithmic flops of one block's value + gradient: joint factorisation and
+    solves (p^3/3 + p^2), covariance generation (30 flop-equivalents per lower-
+    triangle entry) and the adjoint's extra work (3 m^2 l + 2 m^2)."""
+    return p ** 3 / 3.0 + p ** 2 + 30.0 * p * (p + 1) / 2.0 + 3.0 * m * m * l + 2.0 * m * m
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="C3")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (HBM counter calibration under rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2410_04477_amd import api
+    from paper_2410_04477_amd.model import BlockVecchia
+
+    w = W.WORKLOADS[args.workload]
+    dev = torch.device("cuda:0")
+    th0 = w.theta
+    t_setup = time.perf_counter()
+
+    # ---- synthetic data: sequential Vecchia draw (sim_m neighbours) ----------
+    locs = W.locations(w)
+    order = W.point_permutation(w.n, w.seed_y)
+    inv_order = np.argsort(order)
+    metric = list(w.metric_scale)
+    locs_ord = torch.tensor(locs[order], device=dev)
+    unit = torch.arange(w.n + 1, dtype=torch.int32, device=dev)
+    log(f"simulating y: n={w.n}, {w.sim_m} neighbours")
+    snptr, snidx = api.neighbors(locs_ord, unit, w.sim_m, metric)
+    z = torch.tensor(W.standard_normal(w.n, w.seed_y), device=dev)
+    y_ord = api.simulate(locs_ord, snptr, snidx, (th0.sigma2, th0.beta, th0.nugget, th0.nu, th0.aniso), z)
+    y = api.permute_rows(y_ord, torch.tensor(inv_order, device=dev))
+    del snptr, snidx, locs_ord, unit, y_ord, z
+    torch.cuda.synchronize()
+    t_sim = time.perf_counter() - t_setup
+
+    # ---- preprocessing: K-means blocks, random order, neighbours, plan -------
+    log(f"preprocessing: bc={w.bc}, m={w.m}")
+    t1 = time.perf_counter()
+    model = BlockVecchia(locs, y, w.bc, w.m, th0.nu, W.kmeans_init(w.n, w.bc, w.seed_kmeans),
+                         W.block_permutation(w.bc, w.seed_kmeans), th0.aniso[: w.d], w.kmeans_iters)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t1
+    plan = model.plan
+    thetas = [model.theta(t.sigma2, t.beta, t.nugget) for t in W.theta_cycle_c3(w)]
+    log(f"setup done: simulate {t_sim:.1f}s, preprocess {t_pre:.1f}s, kmeans iters {model.kmeans_iters}, "
+        f"buckets {plan.buckets()}")
+
+    def run(precision: str, grad: bool, k: int) -> None:
+        for i in range(k):
+            th = [thetas[i % len(thetas)]]
+            if grad:
+                model.loglik_grad(th, precision)
+            else:
+                model.loglik(th, precision)
+
+    def timed(precision: str, grad: bool, k: int, warm: int, with_timing: bool = False):
+        run(precision, grad, warm)
+        torch.cuda.synchronize()
+        if with_timing:
+            plan.set_timing(True)
+            plan.timing(reset=True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev0.record()
+        run(precision, grad, k)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kt = plan.timing(reset=True) if with_timing else None
+        if with_timing:
+            plan.set_timing(False)
+        return wall, ev0.elapsed_time(ev1) / 1e3, kt
+
+    # ---- headline: FP32-bulk value + gradient --------------------------------
+    log(f"timing fp32-bulk loglik+grad: warmup {args.warmup}, steps {args.steps}")
+    wall, gpu_s, kt = timed("fp32", True, args.steps, args.warmup, with_timing=True)
+    ms_step = 1e3 * wall / args.steps
+    evals = args.steps / wall
+
+    # ---- roofline of the dominant kernel (live HIP events) -------------------
+    bp = plan.block_ptr.cpu().numpy().astype(np.int64)
+    npt = plan.nbr_ptr.cpu().numpy().astype(np.int64)
+    lsz, msz = np.diff(bp), np.diff(npt)
+    psz = lsz + msz
+    sched = plan.schedule().cpu().numpy()
+    qdom = int(np.argmax([ms for ms, _ in kt]))
+    ms_dom, n_dom = kt[qdom]
+    cfg_dom = plan.buckets()[qdom][0]
+    off0, off1 = int(plan.c.bucket_off[qdom]), int(plan.c.bucket_off[qdom + 1])
+    blk = sched[off0:off1]
+    flops_launch = float(np.sum(step_flops(psz[blk].astype(np.float64), msz[blk].astype(np.float64),
+                                           lsz[blk].astype(np.float64))))
+    avg_launch_s = ms_dom / n_dom / 1e3
+    achieved = flops_launch / avg_launch_s
+    R, G = api.tile_config(cfg_dom)
+    traffic = None
+    tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if os.path.exists(tpath):
+        with open(tpath) as fh:
+            tr = json.load(fh)
+        ent = tr.get(f"bv_adj_kernel<float,{R},{G}>")
+        if ent and tr.get("kernel_source_sha") == kernel_source_sha():
+            traffic = ent.get("bytes_per_launch")
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
+                "frac": achieved / FP32_VECTOR_PEAK, "traffic": traffic,
+                "kernel": f"bv_adj_kernel<float,{R},{G}>", "blocks_per_launch": int(blk.size),
+                "avg_launch_ms": avg_launch_s * 1e3, "flops_per_launch": flops_launch,
+                "share_of_step": ms_dom / (1e3 * gpu_s) if gpu_s > 0 else None}
+    total_flops_step = float(np.sum(step_flops(psz.astype(np.float64), msz.astype(np.float64),
+                                               lsz.astype(np.float64))))
+
+    # ---- variants and accuracy ----------------------------------------------
+    variants = {}
+    if not args.no_variants:
+        k2 = max(3, args.steps // 2)
+        for prec, grad in (("fp64", True), ("fp64", False), ("fp32", False)):
+            log(f"timing {prec} {'loglik+grad' if grad else 'loglik'}")
+            wv, _, _ = timed(prec, grad, k2, 1)
+            variants[f"{prec}_{'loglik_grad' if grad else 'loglik'}_evals_per_s"] = k2 / wv
+        variants["fp32_loglik_grad_evals_per_s"] = evals
+        variants["speedup_fp32_over_fp64_loglik_grad"] = evals / variants["fp64_loglik_grad_evals_per_s"]
+        variants["speedup_fp32_over_fp64_loglik"] = (variants["fp32_loglik_evals_per_s"]
+                                                     / variants["fp64_loglik_evals_per_s"])
+    tt = [thetas[0]]
+    l64, g64, _, _, _ = model.loglik_grad(tt, "fp64")
+    l32, g32, c32, _, _ = model.loglik_grad(tt, "fp32")
+    l64, l32 = float(l64[0]), float(l32[0])
+    g64n, g32n = g64[0].cpu().numpy(), g32[0].cpu().numpy()
+    accuracy = {"loglik_fp64": l64, "loglik_fp32": l32, "rel_err_loglik_fp32_vs_fp64": abs(l32 - l64) / abs(l64),
+                "rel_err_grad_fp32_vs_fp64": float(np.linalg.norm(g32n - g64n) / np.linalg.norm(g64n)),
+                "fp32_blocks_refactored": int(c32[0, 0]), "blocks": int(plan.bc)}
+
+    # ---- CPU baseline: the FP64 oracle on a bounded sample of the same blocks --
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(model, plan, bp, npt, th0, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": evals,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: n={w.n} {w.d}-D, nu={th0.nu}, sigma2={th0.sigma2}, "
+                               f"ranges {[th0.beta * a for a in th0.aniso[:w.d]]}, nugget={th0.nugget}, "
+                               f"bc={w.bc}, m={w.m}, y by sequential Vecchia ({w.sim_m} nbrs)",
+                   "step": "loglik + adjoint gradient (sigma2, range, nugget)",
+                   "precision": "fp32-bulk, fp64 accumulation and guard re-factorisation",
+                   "n": w.n, "bc": int(plan.bc), "m": w.m},
+        "points_per_s": evals * w.n,
+        "gflops_per_step": total_flops_step / 1e9,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "variants": variants,
+        "accuracy": accuracy,
+        "setup_s": {"simulate": t_sim, "preprocess": t_pre},
+    }
+    if args.copy_calibration:
+        src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = 2 * src.numel() * 8
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def cpu_baseline(model, plan, bp, npt, th0, target_s):
+    """FP64 oracle (plain C, OpenMP over blocks) value + gradient on a seeded
+    random sample of the workload's blocks, scaled to evaluations per second of
+    the whole workload.  Timing only."""
+    import numpy as np
+
+    import workloads as W
+    from oracle import coracle
+
+    locs = model.locs_perm.cpu().numpy()
+    y = model.y_perm.cpu().numpy()
+    nidx = model.nbr_idx.cpu().numpy().astype(np.int64)
+    cores = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    bc = plan.bc
+    order = W.rng(12345).permutation(bc)
+
+    def run(S):
+        t0 = time.perf_counter()
+        coracle.selected_terms(locs, y, bp, npt, nidx, th0, order[:S], with_grad=True, nthreads=cores)
+        return time.perf_counter() - t0
+
+    S = min(bc, 64)
+    dt = run(S)
+    S2 = int(min(bc, max(S, S * target_s / max(dt, 1e-3))))
+    dt = run(S2)
+    per_eval = dt * bc / S2
+    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": cores, "kind": "oracle",
+            "sample": f"{S2} of {bc} blocks (seeded random), FP64 loglik + gradient, scaled by {bc}/{S2}",
+            "seconds": dt}
+
+
+if __name__ == "__main__":
+    sys.exit(main())

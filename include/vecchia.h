@@ -154,12 +154,26 @@ typedef struct {
   void* ws;
   size_t ws_bytes;
   size_t off_sched, off_partial, off_flag, off_list, off_count, off_chunk, off_grad;
+  void* timing;   /* NULL unless vecchia_plan_set_timing enabled per-launch timing */
 } vecchia_plan;
 
 size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
+/* Register-tile configuration of a size class (plan->bucket_cfg[q]): tile
+ * size R and tile-grid order G, joint capacity R*G.  Returns VECCHIA_EINVAL for
+ * an unknown configuration. */
+int vecchia_tile_config(int32_t cfg, int32_t* R, int32_t* G);
 int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, const int32_t* nbr_ptr,
                       int64_t n, int64_t bc, int32_t max_theta,
                       void* workspace, size_t ws_bytes, void* stream);
+
+/* Per-launch timing for benchmarks.  When enabled, vecchia_loglik and
+ * vecchia_loglik_grad bracket every size-class kernel launch with hipEvents
+ * recorded on the call's stream (host-side objects; no device memory).
+ * vecchia_plan_timing synchronises those events and returns, per size class
+ * q < plan->nbuckets, the summed milliseconds of its main kernel launches and
+ * their count; reset != 0 clears the record.  Disabling frees the events. */
+int vecchia_plan_set_timing(vecchia_plan* plan, int enable);
+int vecchia_plan_timing(vecchia_plan* plan, double* ms, int64_t* launches, int reset);
 
 /* ---------------------------------------------------------------- loglik --
  * Block Vecchia log-likelihood (Alg. 1) for ntheta parameter vectors.
@@ -181,6 +195,39 @@ int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm, const doub
                    const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
                    const vecchia_theta* theta, int32_t ntheta, int32_t precision,
                    double* loglik, int32_t* counters, double* partial, void* stream);
+
+/* ----------------------------------------------------------- loglik_grad --
+ * Log-likelihood and its gradient w.r.t. (sigma2, range, nugget) for each
+ * theta.  The gradient is the adjoint of the per-block chain of Alg. 1,
+ * evaluated without storing any factor: each workgroup re-factorises its
+ * block, back-substitutes once with L_J^T for [alpha | b | R^T] and contracts
+ * against the covariance derivatives regenerated on the fly, where
+ *   d l_i = 1/2 [alpha^T dK_J alpha - b^T dK_N b - <K_J^-1 - K_N^-1, dK_J>].
+ * "range" is the common scale: with anisotropy, d/d(range) scales every axis.
+ * Arguments as vecchia_loglik, plus
+ *   grad      out, 3*ntheta doubles [t*3 + k], k = (sigma2, range, nugget)
+ *   gpartial  out or NULL, ntheta*bc*3 doubles, per-block gradient rows
+ * The FP32-bulk path re-runs guard-flagged blocks (value and gradient) in FP64. */
+int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                        const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                        const vecchia_theta* theta, int32_t ntheta, int32_t precision,
+                        double* loglik, double* grad, int32_t* counters, double* partial, double* gpartial,
+                        void* stream);
+
+/* -------------------------------------------------------------- simulate --
+ * Sequential Vecchia simulator (data generator of the synthetic workloads):
+ * points in the given order, y_i = c_i^T y_{N(i)} + sqrt(s_i) z_i, where N(i)
+ * (nbr_ptr / nbr_idx, every index < i) are earlier points, c_i = K_NN^-1 k_Ni and
+ * s_i = k_ii - k_Ni^T c_i (FP64).  Neighbour lists for it come from
+ * vecchia_neighbors with unit blocks (block_ptr = 0..n).
+ *   locs_ord  n x d, simulation order;  z: n innovations;  y: out, n values
+ *   workspace >= vecchia_simulate_workspace_size(n, nbr_ptr[n]) bytes
+ * Every neighbour set must satisfy m_i + 1 <= VECCHIA_MAX_JOINT.
+ * Synchronises `stream`. */
+size_t vecchia_simulate_workspace_size(int64_t n, int64_t nnz);
+int vecchia_simulate(const double* locs_ord, int64_t n, int32_t d, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                     const vecchia_theta* theta, const double* z, double* y,
+                     void* workspace, size_t ws_bytes, void* stream);
 
 #ifdef __cplusplus
 }

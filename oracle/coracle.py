@@ -35,6 +35,12 @@ def lib():
             f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]
+        for name in ("bvo_loglik_sel", "bvo_grad_sel"):
+            f = getattr(L, name)
+            f.restype = ctypes.c_int64
+            f.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                          ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32]
         f = L.bvo_simulate
         f.restype = ctypes.c_int64
         f.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
@@ -116,3 +122,25 @@ def simulate(locs_perm, block_ptr, nbr_ptr, nbr_idx, theta, z):
     if bad:
         raise ValueError(f"{bad} blocks not positive definite in simulation")
     return y
+
+
+def selected_terms(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta, sel, with_grad=False, nthreads=0):
+    """Per-block terms (and gradient rows) of the blocks listed in sel only."""
+    locs = _c(locs_perm, np.float64)
+    y = _c(y_perm, np.float64)
+    bp = _c(block_ptr, np.int64)
+    npt = _c(nbr_ptr, np.int64)
+    ni = _c(nbr_idx, np.int64) if len(nbr_idx) else np.zeros(1, np.int64)
+    sl = _c(sel, np.int64)
+    th = _theta7(theta)
+    out = np.empty(sl.size)
+    lib().bvo_loglik_sel(locs.ctypes.data, y.ctypes.data, locs.shape[0], locs.shape[1], bp.ctypes.data,
+                         bp.size - 1, npt.ctypes.data, ni.ctypes.data, th.ctypes.data, sl.ctypes.data, sl.size,
+                         out.ctypes.data, nthreads)
+    if not with_grad:
+        return out
+    g = np.empty((sl.size, 3))
+    lib().bvo_grad_sel(locs.ctypes.data, y.ctypes.data, locs.shape[0], locs.shape[1], bp.ctypes.data,
+                       bp.size - 1, npt.ctypes.data, ni.ctypes.data, th.ctypes.data, sl.ctypes.data, sl.size,
+                       g.ctypes.data, nthreads)
+    return out, g

@@ -192,9 +192,9 @@ static int max_block(const int64_t* block_ptr, int64_t bc, const int64_t* nbr_pt
 
 /* Per-block log-likelihood terms.  Returns the number of non-PD blocks (their
  * terms are NaN). */
-int64_t bvo_loglik(const double* locs, const double* y, int64_t n, int32_t d,
-                   const int64_t* block_ptr, int64_t bc, const int64_t* nbr_ptr, const int64_t* nbr_idx,
-                   const double* theta7, double* partial, int32_t nthreads) {
+int64_t bvo_loglik_sel(const double* locs, const double* y, int64_t n, int32_t d,
+                       const int64_t* block_ptr, int64_t bc, const int64_t* nbr_ptr, const int64_t* nbr_idx,
+                       const double* theta7, const int64_t* sel, int64_t nsel, double* partial, int32_t nthreads) {
   (void)n;
   bvo_theta th = {theta7[0], theta7[1], theta7[2], theta7[3], {theta7[4], theta7[5], theta7[6]}};
   int lmax, mmax;
@@ -208,10 +208,11 @@ int64_t bvo_loglik(const double* locs, const double* y, int64_t n, int32_t d,
   {
     double* work = (double*)malloc(sizeof(double) * wsz);
 #pragma omp for schedule(dynamic, 16)
-    for (int64_t i = 0; i < bc; ++i) {
+    for (int64_t q = 0; q < nsel; ++q) {
+      int64_t i = sel ? sel[q] : q;
       int m = (int)(nbr_ptr[i + 1] - nbr_ptr[i]);
       double v = block_loglik(locs, y, d, block_ptr[i], block_ptr[i + 1], nbr_idx + nbr_ptr[i], m, &th, work);
-      partial[i] = v;
+      partial[q] = v;
       if (isnan(v)) bad += 1;
     }
     free(work);
@@ -220,9 +221,9 @@ int64_t bvo_loglik(const double* locs, const double* y, int64_t n, int32_t d,
 }
 
 /* Per-block gradient rows gpartial[3*i + k], k = (sigma2, beta, nugget). */
-int64_t bvo_grad(const double* locs, const double* y, int64_t n, int32_t d,
-                 const int64_t* block_ptr, int64_t bc, const int64_t* nbr_ptr, const int64_t* nbr_idx,
-                 const double* theta7, double* gpartial, int32_t nthreads) {
+int64_t bvo_grad_sel(const double* locs, const double* y, int64_t n, int32_t d,
+                     const int64_t* block_ptr, int64_t bc, const int64_t* nbr_ptr, const int64_t* nbr_idx,
+                     const double* theta7, const int64_t* sel, int64_t nsel, double* gpartial, int32_t nthreads) {
   (void)n;
   bvo_theta th = {theta7[0], theta7[1], theta7[2], theta7[3], {theta7[4], theta7[5], theta7[6]}};
   int lmax, mmax;
@@ -238,7 +239,8 @@ int64_t bvo_grad(const double* locs, const double* y, int64_t n, int32_t d,
     double* work = (double*)malloc(sizeof(double) * wsz);
     int64_t* J = (int64_t*)malloc(sizeof(int64_t) * (pmax + 1));
 #pragma omp for schedule(dynamic, 8)
-    for (int64_t i = 0; i < bc; ++i) {
+    for (int64_t q = 0; q < nsel; ++q) {
+      int64_t i = sel ? sel[q] : q;
       int m = (int)(nbr_ptr[i + 1] - nbr_ptr[i]);
       int l = (int)(block_ptr[i + 1] - block_ptr[i]);
       for (int k = 0; k < m; ++k) J[k] = nbr_idx[nbr_ptr[i] + k];
@@ -246,13 +248,25 @@ int64_t bvo_grad(const double* locs, const double* y, int64_t n, int32_t d,
       double gj[3], gn[3] = {0.0, 0.0, 0.0};
       int e = logpdf_grad(locs, y, d, J, m + l, &th, gj, work);
       if (!e && m > 0) e = logpdf_grad(locs, y, d, J, m, &th, gn, work);
-      for (int k = 0; k < 3; ++k) gpartial[3 * i + k] = e ? NAN : gj[k] - gn[k];
+      for (int k = 0; k < 3; ++k) gpartial[3 * q + k] = e ? NAN : gj[k] - gn[k];
       if (e) bad += 1;
     }
     free(work);
     free(J);
   }
   return bad;
+}
+
+/* Whole-workload entry points (every block, in order). */
+int64_t bvo_loglik(const double* locs, const double* y, int64_t n, int32_t d, const int64_t* block_ptr, int64_t bc,
+                   const int64_t* nbr_ptr, const int64_t* nbr_idx, const double* theta7, double* partial,
+                   int32_t nthreads) {
+  return bvo_loglik_sel(locs, y, n, d, block_ptr, bc, nbr_ptr, nbr_idx, theta7, NULL, bc, partial, nthreads);
+}
+int64_t bvo_grad(const double* locs, const double* y, int64_t n, int32_t d, const int64_t* block_ptr, int64_t bc,
+                 const int64_t* nbr_ptr, const int64_t* nbr_idx, const double* theta7, double* gpartial,
+                 int32_t nthreads) {
+  return bvo_grad_sel(locs, y, n, d, block_ptr, bc, nbr_ptr, nbr_idx, theta7, NULL, bc, gpartial, nthreads);
 }
 
 /* Sequential simulation from the block Vecchia density (eq. (vecchia-vector)),

@@ -30,7 +30,7 @@ class Plan(ctypes.Structure):
                 ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
                 ("off_sched", ctypes.c_size_t), ("off_partial", ctypes.c_size_t), ("off_flag", ctypes.c_size_t),
                 ("off_list", ctypes.c_size_t), ("off_count", ctypes.c_size_t), ("off_chunk", ctypes.c_size_t),
-                ("off_grad", ctypes.c_size_t)]
+                ("off_grad", ctypes.c_size_t), ("timing", ctypes.c_void_p)]
 
 
 class VecchiaError(RuntimeError):
@@ -52,6 +52,12 @@ SIGNATURES = {
     "vecchia_plan_init": (ctypes.c_int, [P, P, P, I64, I64, I32, P, SZ, P]),
     "vecchia_loglik": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P]),
     "vecchia_permute": (ctypes.c_int, [P, I64, I32, P, P, P]),
+    "vecchia_loglik_grad": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P, P, P]),
+    "vecchia_simulate_workspace_size": (SZ, [I64, I64]),
+    "vecchia_simulate": (ctypes.c_int, [P, I64, I32, P, P, P, P, P, P, SZ, P]),
+    "vecchia_tile_config": (ctypes.c_int, [I32, P, P]),
+    "vecchia_plan_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
+    "vecchia_plan_timing": (ctypes.c_int, [P, P, P, ctypes.c_int]),
 }
 
 _lib = None

@@ -49,6 +49,13 @@ def make_theta(th) -> L.Theta:
     return L.Theta(float(s2), float(rg), float(nug), float(nu), (ctypes.c_double * 3)(*an))
 
 
+def tile_config(cfg: int):
+    """(R, G) of a size-class configuration."""
+    r, g = ctypes.c_int32(0), ctypes.c_int32(0)
+    L.check(L.lib().vecchia_tile_config(cfg, ctypes.byref(r), ctypes.byref(g)), "vecchia_tile_config")
+    return r.value, g.value
+
+
 def permute_rows(src: torch.Tensor, perm: torch.Tensor) -> torch.Tensor:
     """dst[i] = src[perm[i]] (rows), done by the library's gather kernel."""
     _dev_check(src, perm)
@@ -126,6 +133,29 @@ class Plan:
     def cov_entries(self) -> float:
         return float(self.c.cov_entries)
 
+    def set_timing(self, enable: bool) -> None:
+        L.check(L.lib().vecchia_plan_set_timing(ctypes.byref(self.c), 1 if enable else 0), "vecchia_plan_set_timing")
+
+    def timing(self, reset: bool = True):
+        """Per size class: (summed ms of the main kernel launches, launch count)."""
+        nb = int(self.c.nbuckets)
+        ms = (ctypes.c_double * max(nb, 1))()
+        cnt = (ctypes.c_int64 * max(nb, 1))()
+        L.check(L.lib().vecchia_plan_timing(ctypes.byref(self.c), ms, cnt, 1 if reset else 0), "vecchia_plan_timing")
+        return [(float(ms[q]), int(cnt[q])) for q in range(nb)]
+
+    def schedule(self) -> torch.Tensor:
+        """Block ids grouped by size class (device int32 view into the plan workspace)."""
+        off = int(self.c.off_sched)
+        return self.ws[off: off + 4 * self.bc].view(torch.int32)
+
+    def __del__(self):
+        try:
+            if self.c.timing:
+                L.lib().vecchia_plan_set_timing(ctypes.byref(self.c), 0)
+        except Exception:
+            pass
+
     def buckets(self):
         return [(int(self.c.bucket_cfg[q]), int(self.c.bucket_off[q + 1] - self.c.bucket_off[q]))
                 for q in range(self.c.nbuckets)]
@@ -148,3 +178,41 @@ def loglik(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_idx: t
                                    _p(plan.nbr_ptr), _p(nbr_idx), arr, nt, PRECISIONS[precision], _p(out), _p(cnt),
                                    _p(part), _stream(dev)), "vecchia_loglik")
     return out, cnt, part
+
+
+def loglik_grad(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_idx: torch.Tensor,
+                thetas: Iterable, precision: str = "fp64", want_partial: bool = False):
+    """Log-likelihood and its gradient w.r.t. (sigma2, range, nugget) for each theta.
+    Returns (loglik[nt], grad[nt, 3], counters[nt, 2], partial[nt, bc] | None,
+    gpartial[nt, bc, 3] | None) as device tensors."""
+    _dev_check(locs_perm, y_perm, nbr_idx)
+    th = [make_theta(t) for t in thetas]
+    nt = len(th)
+    arr = (L.Theta * nt)(*th)
+    dev = locs_perm.device
+    out = torch.empty(nt, dtype=torch.float64, device=dev)
+    grad = torch.empty((nt, 3), dtype=torch.float64, device=dev)
+    cnt = torch.empty((nt, 2), dtype=torch.int32, device=dev)
+    part = torch.empty((nt, plan.bc), dtype=torch.float64, device=dev) if want_partial else None
+    gpart = torch.empty((nt, plan.bc, 3), dtype=torch.float64, device=dev) if want_partial else None
+    d = 1 if locs_perm.dim() == 1 else locs_perm.shape[1]
+    L.check(L.lib().vecchia_loglik_grad(ctypes.byref(plan.c), _p(locs_perm), _p(y_perm), d, _p(plan.block_ptr),
+                                        _p(plan.nbr_ptr), _p(nbr_idx), arr, nt, PRECISIONS[precision], _p(out),
+                                        _p(grad), _p(cnt), _p(part), _p(gpart), _stream(dev)),
+            "vecchia_loglik_grad")
+    return out, grad, cnt, part, gpart
+
+
+def simulate(locs_ord: torch.Tensor, nbr_ptr: torch.Tensor, nbr_idx: torch.Tensor, theta,
+             z: torch.Tensor) -> torch.Tensor:
+    """Sequential Vecchia draw in the given point order (see vecchia_simulate)."""
+    _dev_check(locs_ord, nbr_ptr, nbr_idx, z)
+    n, d = locs_ord.shape
+    lib = L.lib()
+    nnz = int(nbr_ptr[-1].item())
+    ws = torch.empty(int(lib.vecchia_simulate_workspace_size(n, nnz)), dtype=torch.uint8, device=locs_ord.device)
+    y = torch.empty(n, dtype=torch.float64, device=locs_ord.device)
+    th = make_theta(theta)
+    L.check(lib.vecchia_simulate(_p(locs_ord), n, d, _p(nbr_ptr), _p(nbr_idx), ctypes.byref(th), _p(z), _p(y),
+                                 _p(ws), ws.numel(), _stream(locs_ord.device)), "vecchia_simulate")
+    return y

@@ -79,6 +79,13 @@ bool theta_to_dev(const vecchia_theta& t, int d, ThetaDev& o) {
 template <typename P> P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(base) + off); }
 }  // namespace
 
+extern "C" int vecchia_tile_config(int32_t cfg, int32_t* R, int32_t* G) {
+  if (cfg < 0 || cfg >= kNumCfgs || !R || !G) return VECCHIA_EINVAL;
+  *R = kCfgs[cfg].R;
+  *G = kCfgs[cfg].G;
+  return VECCHIA_OK;
+}
+
 extern "C" size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta) {
   if (bc <= 0 || max_theta <= 0) return 0;
   return plan_layout(bc, max_theta).total;
@@ -92,7 +99,7 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   const PlanLayout L = plan_layout(bc, max_theta);
   if (ws_bytes < L.total) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
-  memset(plan, 0, sizeof(*plan));
+  memset(plan, 0, sizeof(*plan));  // a plan with timing enabled must disable it before re-initialisation
   int* cfg_of = at<int>(workspace, L.scratch);
   int* counts = at<int>(workspace, L.count);            // [0..32) counts, [32..64) cursors/offsets
   unsigned long long* stats = at<unsigned long long>(workspace, L.chunk);
@@ -147,6 +154,70 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   plan->off_count = L.count;
   plan->off_chunk = L.chunk;
   plan->off_grad = L.grad;
+  return VECCHIA_OK;
+}
+
+// -------------------------------------------------------------- timing ----
+
+namespace {
+struct TimingRec {
+  int bucket;
+  hipEvent_t e0, e1;
+};
+struct Timing {
+  std::vector<TimingRec> recs;
+};
+inline hipError_t time_begin(const vecchia_plan* plan, int q, hipStream_t s, TimingRec& r) {
+  r.bucket = q;
+  r.e0 = r.e1 = nullptr;
+  if (!plan->timing) return hipSuccess;
+  hipError_t e = hipEventCreate(&r.e0);
+  if (e == hipSuccess) e = hipEventCreate(&r.e1);
+  if (e == hipSuccess) e = hipEventRecord(r.e0, s);
+  return e;
+}
+inline hipError_t time_end(const vecchia_plan* plan, hipStream_t s, TimingRec& r) {
+  if (!plan->timing) return hipSuccess;
+  hipError_t e = hipEventRecord(r.e1, s);
+  static_cast<Timing*>(plan->timing)->recs.push_back(r);
+  return e;
+}
+void timing_clear(Timing* t) {
+  for (auto& r : t->recs) {
+    hipEventDestroy(r.e0);
+    hipEventDestroy(r.e1);
+  }
+  t->recs.clear();
+}
+}  // namespace
+
+extern "C" int vecchia_plan_set_timing(vecchia_plan* plan, int enable) {
+  if (!plan) return VECCHIA_EINVAL;
+  if (enable && !plan->timing) plan->timing = new Timing();
+  if (!enable && plan->timing) {
+    timing_clear(static_cast<Timing*>(plan->timing));
+    delete static_cast<Timing*>(plan->timing);
+    plan->timing = nullptr;
+  }
+  return VECCHIA_OK;
+}
+
+extern "C" int vecchia_plan_timing(vecchia_plan* plan, double* ms, int64_t* launches, int reset) {
+  if (!plan || !ms || !launches) return VECCHIA_EINVAL;
+  for (int q = 0; q < plan->nbuckets; ++q) {
+    ms[q] = 0.0;
+    launches[q] = 0;
+  }
+  if (!plan->timing) return VECCHIA_OK;
+  Timing* t = static_cast<Timing*>(plan->timing);
+  for (auto& r : t->recs) {
+    VCHECK_HIP(hipEventSynchronize(r.e1));
+    float f = 0.f;
+    VCHECK_HIP(hipEventElapsedTime(&f, r.e0, r.e1));
+    ms[r.bucket] += (double)f;
+    launches[r.bucket] += 1;
+  }
+  if (reset) timing_clear(t);
   return VECCHIA_OK;
 }
 
@@ -207,7 +278,10 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
       const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
       a.sched = sched + plan->bucket_off[q];
       a.nsched = ns;
+      TimingRec tr;
+      VCHECK_HIP(time_begin(plan, q, s, tr));
       VCHECK_HIP(launch_forward(plan->bucket_cfg[q], fp32, a, thp, ns * nt, s));
+      VCHECK_HIP(time_end(plan, s, tr));
     }
     if (fp32) {
       // FP32 guard: compact flagged (theta, block) pairs per size class, re-run them in FP64
@@ -232,6 +306,87 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
                                       counters ? counters + 2 * t0 : nullptr, s));
     if (partial)
       VCHECK_HIP(hipMemcpyAsync(partial + (size_t)t0 * bc, part, sizeof(double) * (size_t)nt * bc,
+                                hipMemcpyDeviceToDevice, s));
+  }
+  return VECCHIA_OK;
+}
+
+// ----------------------------------------------------------- loglik_grad --
+
+extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const double* y_perm,
+                                   int32_t d, const int32_t* block_ptr, const int32_t* nbr_ptr,
+                                   const int32_t* nbr_idx, const vecchia_theta* theta, int32_t ntheta,
+                                   int32_t precision, double* loglik, double* grad, int32_t* counters,
+                                   double* partial, double* gpartial, void* stream) {
+  int st = check_common(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision);
+  if (st) return st;
+  if (!loglik || !grad) return VECCHIA_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  const int bc = (int)plan->bc;
+  void* ws = plan->ws;
+  const bool fp32 = precision != VECCHIA_FP64;
+  const int* sched = at<int>(ws, plan->off_sched);
+  double* part = at<double>(ws, plan->off_partial);
+  double* gpart = at<double>(ws, plan->off_grad);
+  int* flag = at<int>(ws, plan->off_flag);
+  int* list = at<int>(ws, plan->off_list);
+  int* count = at<int>(ws, plan->off_count);
+
+  for (int t0 = 0; t0 < ntheta; t0 += kMaxThetaPerLaunch) {
+    const int nt = ntheta - t0 < kMaxThetaPerLaunch ? ntheta - t0 : kMaxThetaPerLaunch;
+    ThetaPack thp;
+    memset(&thp, 0, sizeof(thp));
+    for (int t = 0; t < nt; ++t) theta_to_dev(theta[t0 + t], d, thp.t[t]);
+    AdjArgs a;
+    memset(&a, 0, sizeof(a));
+    a.locs = locs_perm;
+    a.y = y_perm;
+    a.block_ptr = block_ptr;
+    a.nbr_ptr = nbr_ptr;
+    a.nbr_idx = nbr_idx;
+    a.ntheta = nt;
+    a.bc = bc;
+    a.d = d;
+    a.fp32_guard = precision == VECCHIA_FP32_BULK_FORCE_REFACTOR ? 2 : (fp32 ? 1 : 0);
+    a.ldx = plan->lmax + 2;
+    a.partial = part;
+    a.gpart = gpart;
+    a.flag = flag;
+    for (int q = 0; q < plan->nbuckets; ++q) {
+      const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+      a.sched = sched + plan->bucket_off[q];
+      a.nsched = ns;
+      TimingRec tr;
+      VCHECK_HIP(time_begin(plan, q, s, tr));
+      VCHECK_HIP(launch_adjoint(plan->bucket_cfg[q], fp32, a, thp, ns * nt, s));
+      VCHECK_HIP(time_end(plan, s, tr));
+    }
+    if (fp32) {
+      VCHECK_HIP(launch_fill_int(count, plan->nbuckets, 0, s));
+      for (int q = 0; q < plan->nbuckets; ++q) {
+        const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+        VCHECK_HIP(launch_compact_flagged(sched + plan->bucket_off[q], ns, nt, bc, flag,
+                                          list + plan->bucket_off[q] * nt, count + q, s));
+      }
+      AdjArgs r = a;
+      r.fp32_guard = 0;
+      r.flag_or = 4;
+      for (int q = 0; q < plan->nbuckets; ++q) {
+        const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+        r.list = list + plan->bucket_off[q] * nt;
+        r.list_count = count + q;
+        const int cap = ns * nt;
+        VCHECK_HIP(launch_adjoint(plan->bucket_cfg[q], false, r, thp, cap < 256 ? cap : 256, s));
+      }
+    }
+    VCHECK_HIP(launch_reduce_partials(part, flag, bc, nt, fp32 ? 0 : 1, loglik + t0,
+                                      counters ? counters + 2 * t0 : nullptr, s));
+    VCHECK_HIP(launch_reduce_vec(gpart, bc, 3, nt, grad + 3 * t0, s));
+    if (partial)
+      VCHECK_HIP(hipMemcpyAsync(partial + (size_t)t0 * bc, part, sizeof(double) * (size_t)nt * bc,
+                                hipMemcpyDeviceToDevice, s));
+    if (gpartial)
+      VCHECK_HIP(hipMemcpyAsync(gpartial + (size_t)t0 * bc * 3, gpart, sizeof(double) * (size_t)nt * bc * 3,
                                 hipMemcpyDeviceToDevice, s));
   }
   return VECCHIA_OK;

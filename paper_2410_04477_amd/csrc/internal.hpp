@@ -26,6 +26,32 @@ struct FwdArgs {
 
 hipError_t launch_forward(int cfg, bool fp32, const FwdArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 
+struct AdjArgs {
+  const double* locs;
+  const double* y;
+  const int* block_ptr;
+  const int* nbr_ptr;
+  const int* nbr_idx;
+  const int* sched;
+  const int* list;
+  const int* list_count;
+  int nsched;
+  int ntheta;
+  int bc;
+  int d;
+  int fp32_guard;
+  int flag_or;
+  int ldx;               // leading dimension of the LDS right-hand sides (>= l_max + 2)
+  double* partial;       // [theta * bc + block]
+  double* gpart;         // [(theta * bc + block) * 3 + k]
+  int* flag;
+  double* coef;          // coefficient mode: conditional-mean weights, CSR like nbr_idx
+  double* cvar;          // coefficient mode: conditional variance per block
+};
+
+hipError_t launch_adjoint(int cfg, bool fp32, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+hipError_t launch_coefficients(int cfg, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+
 hipError_t launch_classify(const int* block_ptr, const int* nbr_ptr, int bc, int* cfg_of, int* counts,
                            unsigned long long* stats, int* maxes, hipStream_t s);
 hipError_t launch_scatter(const int* cfg_of, int bc, const int* cfg_off, int* cursor, int* sched, hipStream_t s);

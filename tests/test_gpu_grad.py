@@ -1,0 +1,142 @@
+"""GPU adjoint gradient and simulator against the oracle.
+
+Gradient tolerances (norm-wise, ||dg|| / ||g||): FP64 adjoint vs the oracle's
+trace-formula gradient <= 1e-8; vs central finite differences of the FP64
+log-likelihood (h = 1e-5 absolute on the natural parameters) within their
+own step-halving truncation estimate, and vs the Richardson-extrapolated
+difference <= 1e-6; FP32-bulk gradient vs FP64 <= 1e-3."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from cases import problem, workload_problem
+from oracle import coracle
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _model(pb, nu, aniso=(1.0, 1.0, 1.0), max_theta=1):
+    from paper_2410_04477_amd.model import BlockVecchia
+    t = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device=DEV)
+    nidx = pb["nbr_idx"] if len(pb["nbr_idx"]) else np.zeros(1)
+    return BlockVecchia.from_prepared(t(pb["locs_perm"], torch.float64), t(pb["y_perm"], torch.float64),
+                                      t(pb["block_ptr"], torch.int32), t(pb["nbr_ptr"], torch.int32),
+                                      t(nidx, torch.int32), nu, aniso, max_theta)
+
+
+def _oracle_grad(pb, th):
+    return coracle.grad_terms(pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"], th)
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+@pytest.mark.parametrize("m,bc,nu,d", [(0, 60, 1.5, 2), (12, 60, 0.5, 2), (30, 100, 1.5, 2), (60, 100, 2.5, 3),
+                                       (100, 120, 1.5, 2), (140, 300, 2.5, 3), (160, 600, 0.5, 2)])
+def test_adjoint_matches_oracle_per_block(m, bc, nu, d):
+    aniso = (1.0, 1.0, 0.3) if d == 3 else (1.0, 1.0, 1.0)
+    th = W.Theta(1.2, 0.06, 2e-3, nu, aniso)
+    pb = problem(f"g{m}", 1500, d, bc, m, th, 50 + m, zmax=0.3)
+    mod = _model(pb, nu, aniso)
+    ll, g, cnt, part, gpart = mod.loglik_grad([mod.theta(th.sigma2, th.beta, th.nugget)], "fp64", True)
+    ref = _oracle_grad(pb, th)
+    gp = gpart[0].cpu().numpy()
+    np.testing.assert_allclose(gp, ref, rtol=1e-7, atol=1e-8 * np.abs(ref).max())
+    assert _rel(g[0].cpu().numpy(), ref.sum(0)) <= 1e-8
+    # the value path of the adjoint kernel equals the forward kernel's
+    llf = mod.loglik([mod.theta(th.sigma2, th.beta, th.nugget)])[0]
+    assert abs(float(ll[0]) - float(llf[0])) <= 1e-12 * abs(float(llf[0]))
+
+
+def test_adjoint_vs_central_fd_and_fp32():
+    """Central differences with h = 1e-5 (absolute, natural parameters).  Their
+    truncation error is O(h^2 f3) (f3 the third derivative), which grows like
+    1/nugget^2 relative, so the check uses the step-halving estimate of that
+    error and a Richardson-extrapolated difference (error O(h^4))."""
+    th = W.Theta(1.5, 0.08, 0.01, 1.5)
+    pb = problem("fd", 6000, 2, 600, 50, th, 61, ysim="block")
+    mod = _model(pb, 1.5)
+    base = (th.sigma2, th.beta, th.nugget)
+    _, g, _, _, _ = mod.loglik_grad([mod.theta(*base)], "fp64")
+    g = g[0].cpu().numpy()
+
+    def fd(h):
+        out = []
+        for k in range(3):
+            up, dn = list(base), list(base)
+            up[k] += h
+            dn[k] -= h
+            lu = float(mod.loglik([mod.theta(*up)])[0][0])
+            ld = float(mod.loglik([mod.theta(*dn)])[0][0])
+            out.append((lu - ld) / (2 * h))
+        return np.array(out)
+
+    f1, f2 = fd(1e-5), fd(0.5e-5)
+    rich = (4 * f2 - f1) / 3
+    trunc = np.abs(f1 - f2) * 4 / 3
+    print("adjoint", g, "fd(1e-5)", f1, "richardson", rich)
+    assert np.all(np.abs(g - f1) <= 1.5 * trunc + 1e-7 * np.linalg.norm(g))
+    assert _rel(g, rich) <= 1e-6
+    _, g32, _, _, _ = mod.loglik_grad([mod.theta(*base)], "fp32")
+    assert _rel(g32[0].cpu().numpy(), g) <= 1e-3
+
+
+def test_fp32_forced_refactor_gradient_equals_fp64():
+    th = W.Theta(1.0, 0.05, 1e-3, 2.5)
+    pb = problem("gforce", 2000, 2, 200, 40, th, 62, ysim="block")
+    mod = _model(pb, 2.5)
+    t = [mod.theta(th.sigma2, th.beta, th.nugget)]
+    l64, g64, _, _, _ = mod.loglik_grad(t, "fp64")
+    lf, gf, cnt, _, _ = mod.loglik_grad(t, "fp32_force_refactor")
+    assert int(cnt[0, 0]) == 200
+    assert torch.equal(g64, gf) and torch.equal(l64, lf)
+
+
+def test_c4_full_size_gradient_vs_oracle():
+    """n = 200,000, 20,000 blocks, m = 100: adjoint at theta0 and at the truth."""
+    w = W.C4
+    pb = workload_problem(w, ysim="block")
+    mod = _model(pb, 1.5, max_theta=2)
+    thetas = [W.Theta(*W.C4_THETA0, 1.5), w.theta]
+    ll, g, cnt, _, _ = mod.loglik_grad([mod.theta(t.sigma2, t.beta, t.nugget) for t in thetas], "fp64")
+    ll32, g32, _, _, _ = mod.loglik_grad([mod.theta(t.sigma2, t.beta, t.nugget) for t in thetas], "fp32")
+    for i, th in enumerate(thetas):
+        ref = _oracle_grad(pb, th).sum(0)
+        assert _rel(g[i].cpu().numpy(), ref) <= 1e-8
+        assert _rel(g32[i].cpu().numpy(), ref) <= 1e-3
+        ref_ll = coracle.loglik(pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"], th)
+        assert abs(float(ll[i]) - ref_ll) <= 1e-8 * abs(ref_ll)
+        assert abs(float(ll32[i]) - ref_ll) <= 1e-4 * abs(ref_ll)
+
+
+def test_simulator_matches_oracle():
+    from paper_2410_04477_amd import api
+    from oracle.preprocess import point_neighbors
+    n, m = 4000, 150
+    th = W.Theta(1.0, 0.05, 1e-3, 2.5, (1.0, 1.0, 0.2))
+    s = W.rng(71).random((n, 3)) * [1, 1, 0.2]
+    order = W.point_permutation(n, 71)
+    so = s[order]
+    w = [1.0, 1.0, 5.0]
+    ptr, idx = point_neighbors(so * w, m)
+    z = W.standard_normal(n, 72)
+    ref = coracle.simulate(so, np.arange(n + 1), ptr, idx, th, z)
+    t = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device=DEV)
+    y = api.simulate(t(so, torch.float64), t(ptr, torch.int32), t(idx, torch.int32), th, t(z, torch.float64))
+    np.testing.assert_allclose(y.cpu().numpy(), ref, rtol=1e-9, atol=1e-9)
+
+
+def test_mle_recovers_parameters_and_beats_start():
+    from paper_2410_04477_amd import mle
+    th = W.Theta(1.5, 0.08, 0.01, 1.5)
+    pb = problem("mle", 8000, 2, 800, 40, th, 81, ysim="block")
+    mod = _model(pb, 1.5)
+    res = mle.fit(mod, W.C4_THETA0, "fp64", max_evals=80)
+    ll_true = float(mod.loglik([mod.theta(th.sigma2, th.beta, th.nugget)])[0][0])
+    ll0 = float(mod.loglik([mod.theta(*W.C4_THETA0)])[0][0])
+    assert res.loglik >= ll_true - 1e-6 * abs(ll_true)   # the MLE is at least as likely as the truth
+    assert res.loglik > ll0
+    assert 0.5 < res.theta[0] / th.sigma2 < 2.0 and 0.5 < res.theta[1] / th.beta < 2.0
