@@ -219,15 +219,59 @@ int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const
  * points in the given order, y_i = c_i^T y_{N(i)} + sqrt(s_i) z_i, where N(i)
  * (nbr_ptr / nbr_idx, every index < i) are earlier points, c_i = K_NN^-1 k_Ni and
  * s_i = k_ii - k_Ni^T c_i (FP64).  Neighbour lists for it come from
- * vecchia_neighbors with unit blocks (block_ptr = 0..n).
- *   locs_ord  n x d, simulation order;  z: n innovations;  y: out, n values
- *   workspace >= vecchia_simulate_workspace_size(n, nbr_ptr[n]) bytes
+ * vecchia_neighbors with unit blocks (block_ptr = 0..n).  ntheta <= 24 data sets
+ * that share the design (locations and neighbours) are drawn in one call.
+ *   locs_ord  n x d, simulation order
+ *   theta     host, ntheta parameter vectors
+ *   z         ntheta x n innovations;  y: out, ntheta x n values
+ *   workspace >= vecchia_simulate_workspace_size(n, nbr_ptr[n], ntheta) bytes
  * Every neighbour set must satisfy m_i + 1 <= VECCHIA_MAX_JOINT.
  * Synchronises `stream`. */
-size_t vecchia_simulate_workspace_size(int64_t n, int64_t nnz);
+size_t vecchia_simulate_workspace_size(int64_t n, int64_t nnz, int32_t ntheta);
 int vecchia_simulate(const double* locs_ord, int64_t n, int32_t d, const int32_t* nbr_ptr, const int32_t* nbr_idx,
-                     const vecchia_theta* theta, const double* z, double* y,
+                     const vecchia_theta* theta, int32_t ntheta, const double* z, double* y,
                      void* workspace, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------- warm start --
+ * Kernels of the learned warm start (variogram features -> MLP -> theta_0).
+ *
+ * vecchia_variogram: binned empirical semivariogram of nsets data sets, each a
+ * subset of k two-dimensional points (locs: nsets blocks of k x 2 doubles at
+ * stride locs_stride elements, stride 0 = one shared design; y: nsets x k at
+ * stride y_stride).  Pair (i, j), i < j, with 0 < h <= hmax goes to bin
+ * floor(h / hmax * nbins) (FP64, clamped to nbins - 1); gamma_b = sum (y_i - y_j)^2 /
+ * (2 N_b) (0 if N_b = 0).  features: out, nsets x (nslots * nbins) FP32, zero except
+ * slot nu_slot[s]: gamma / subset variance.  gamma: out or NULL, nsets x nbins FP64.
+ * nchunks: workgroups per data set (partial sums reduced in a fixed order).
+ * nbins <= 64. */
+size_t vecchia_variogram_workspace_size(int32_t nsets, int32_t nbins, int32_t nchunks);
+int vecchia_variogram(const double* locs, int64_t locs_stride, const double* y, int64_t y_stride, int32_t nsets,
+                      int32_t k, int32_t nbins, double hmax, const int32_t* nu_slot, int32_t nslots,
+                      float* features, double* gamma, int32_t nchunks, void* workspace, size_t ws_bytes,
+                      void* stream);
+
+/* vecchia_gemm: C (M x N, row-major, ld ldc) = op(A) op(B) [+ bias] with
+ * optional epilogue: act = 1 applies ReLU (Z, if non-NULL, receives the
+ * pre-activation); mask != NULL zeroes entries where mask <= 0 (ReLU backward);
+ * accumulate = 1 adds into C.  op(A) = A (M x K, ld lda) or A^T if ta (A stored
+ * K x M); op(B) = B (K x N, ld ldb) or B^T if tb (B stored N x K).  use_bf16 = 1
+ * rounds operands to BF16 (nearest even) and multiplies on the matrix cores
+ * with FP32 accumulation; 0 uses FP32 FMAs.  All FP32 device arrays. */
+int vecchia_gemm(const float* A, const float* B, float* C, const float* bias, const float* mask, float* Z,
+                 int32_t M, int32_t N, int32_t K, int32_t lda, int32_t ldb, int32_t ldc, int32_t ta, int32_t tb,
+                 int32_t act, int32_t accumulate, int32_t use_bf16, void* stream);
+
+/* vecchia_mse: mean squared error over `total` entries; dout = 2 (out - target) /
+ * total; loss_part[g] = workgroup g's share of the mean (sum them). */
+int vecchia_mse(const float* out, const float* target, int32_t total, float* dout, double* loss_part,
+                int32_t nparts, void* stream);
+
+/* vecchia_colsum: out[n] = sum_m X[m * ld + n] (bias gradients). */
+int vecchia_colsum(const float* X, int32_t M, int32_t N, int32_t ld, float* out, void* stream);
+
+/* vecchia_adam: one Adam step (bias-corrected, step >= 1) on n FP32 parameters. */
+int vecchia_adam(float* param, const float* grad, float* m, float* v, int64_t n, double lr, double beta1,
+                 double beta2, double eps, int64_t step, void* stream);
 
 #ifdef __cplusplus
 }

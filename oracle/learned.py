@@ -53,6 +53,20 @@ def targets(sigma2, beta, nugget) -> np.ndarray:
     return np.array([np.log(sigma2), np.log(beta), np.log(nugget + NUG_EPS)])
 
 
+def bf16_round(x):
+    """Round to the nearest BF16 value (8-bit exponent, 8-bit significand,
+    ties to even), returned as float64.  Used to give the oracle the same
+    operand precision as a BF16 matrix product with FP32 accumulation."""
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.float32))
+    u = a.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _ident(x):
+    return x
+
+
 def init_params(seed: int, sizes=(96, 256, 256, 3)):
     """He-uniform initialisation (seeded) -- weights W_k are (out, in)."""
     g = np.random.Generator(np.random.PCG64(seed))
@@ -64,34 +78,35 @@ def init_params(seed: int, sizes=(96, 256, 256, 3)):
     return ps
 
 
-def forward(params, X):
-    """X: batch x 96.  Returns (out, cache)."""
+def forward(params, X, rnd=_ident):
+    """X: batch x 96.  Returns (out, cache).  rnd rounds every matrix-product
+    operand (identity = exact FP64)."""
     W1, b1, W2, b2, W3, b3 = params
-    z1 = X @ W1.T + b1
+    z1 = rnd(X) @ rnd(W1).T + b1
     a1 = np.maximum(z1, 0.0)
-    z2 = a1 @ W2.T + b2
+    z2 = rnd(a1) @ rnd(W2).T + b2
     a2 = np.maximum(z2, 0.0)
-    out = a2 @ W3.T + b3
+    out = rnd(a2) @ rnd(W3).T + b3
     return out, (X, z1, a1, z2, a2)
 
 
-def mse_backward(params, cache, out, T):
-    """Loss = mean over batch and outputs of (out - T)^2.  Returns (loss, grads)."""
+def mse_backward(params, cache, out, T, rnd=_ident):
+    """Loss = mean over batch and outputs of (out - T)^2.  Returns (loss, grads).
+    rnd rounds every matrix-product operand."""
     W1, b1, W2, b2, W3, b3 = params
     X, z1, a1, z2, a2 = cache
-    B = X.shape[0]
     diff = out - T
     loss = float(np.mean(diff * diff))
     dout = 2.0 * diff / diff.size
-    gW3 = dout.T @ a2
+    gW3 = rnd(dout).T @ rnd(a2)
     gb3 = dout.sum(0)
-    da2 = dout @ W3
+    da2 = rnd(dout) @ rnd(W3)
     dz2 = da2 * (z2 > 0)
-    gW2 = dz2.T @ a1
+    gW2 = rnd(dz2).T @ rnd(a1)
     gb2 = dz2.sum(0)
-    da1 = dz2 @ W2
+    da1 = rnd(dz2) @ rnd(W2)
     dz1 = da1 * (z1 > 0)
-    gW1 = dz1.T @ X
+    gW1 = rnd(dz1).T @ rnd(X)
     gb1 = dz1.sum(0)
     return loss, [gW1, gb1, gW2, gb2, gW3, gb3]
 

@@ -53,8 +53,14 @@ SIGNATURES = {
     "vecchia_loglik": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P]),
     "vecchia_permute": (ctypes.c_int, [P, I64, I32, P, P, P]),
     "vecchia_loglik_grad": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P, P, P]),
-    "vecchia_simulate_workspace_size": (SZ, [I64, I64]),
-    "vecchia_simulate": (ctypes.c_int, [P, I64, I32, P, P, P, P, P, P, SZ, P]),
+    "vecchia_simulate_workspace_size": (SZ, [I64, I64, I32]),
+    "vecchia_simulate": (ctypes.c_int, [P, I64, I32, P, P, P, I32, P, P, P, SZ, P]),
+    "vecchia_variogram_workspace_size": (SZ, [I32, I32, I32]),
+    "vecchia_variogram": (ctypes.c_int, [P, I64, P, I64, I32, I32, I32, D, P, I32, P, P, I32, P, SZ, P]),
+    "vecchia_gemm": (ctypes.c_int, [P, P, P, P, P, P, I32, I32, I32, I32, I32, I32, I32, I32, I32, I32, I32, P]),
+    "vecchia_mse": (ctypes.c_int, [P, P, I32, P, P, I32, P]),
+    "vecchia_colsum": (ctypes.c_int, [P, I32, I32, I32, P, P]),
+    "vecchia_adam": (ctypes.c_int, [P, P, P, P, I64, D, D, D, D, I64, P]),
     "vecchia_tile_config": (ctypes.c_int, [I32, P, P]),
     "vecchia_plan_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
     "vecchia_plan_timing": (ctypes.c_int, [P, P, P, ctypes.c_int]),

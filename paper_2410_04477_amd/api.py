@@ -205,14 +205,74 @@ def loglik_grad(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_i
 
 def simulate(locs_ord: torch.Tensor, nbr_ptr: torch.Tensor, nbr_idx: torch.Tensor, theta,
              z: torch.Tensor) -> torch.Tensor:
-    """Sequential Vecchia draw in the given point order (see vecchia_simulate)."""
+    """Sequential Vecchia draw in the given point order (see vecchia_simulate).
+    theta: one parameter vector (z: n) or a list of up to 24 (z: ntheta x n)."""
     _dev_check(locs_ord, nbr_ptr, nbr_idx, z)
     n, d = locs_ord.shape
     lib = L.lib()
+    many = isinstance(theta, list)
+    ths = [make_theta(t) for t in (theta if many else [theta])]
+    nt = len(ths)
+    arr = (L.Theta * nt)(*ths)
     nnz = int(nbr_ptr[-1].item())
-    ws = torch.empty(int(lib.vecchia_simulate_workspace_size(n, nnz)), dtype=torch.uint8, device=locs_ord.device)
-    y = torch.empty(n, dtype=torch.float64, device=locs_ord.device)
-    th = make_theta(theta)
-    L.check(lib.vecchia_simulate(_p(locs_ord), n, d, _p(nbr_ptr), _p(nbr_idx), ctypes.byref(th), _p(z), _p(y),
+    ws = torch.empty(int(lib.vecchia_simulate_workspace_size(n, nnz, nt)), dtype=torch.uint8,
+                     device=locs_ord.device)
+    y = torch.empty((nt, n) if many else n, dtype=torch.float64, device=locs_ord.device)
+    L.check(lib.vecchia_simulate(_p(locs_ord), n, d, _p(nbr_ptr), _p(nbr_idx), arr, nt, _p(z), _p(y),
                                  _p(ws), ws.numel(), _stream(locs_ord.device)), "vecchia_simulate")
     return y
+
+
+# ----------------------------------------------------------------- warm start
+
+def variogram(locs: torch.Tensor, y: torch.Tensor, nu_slot: torch.Tensor, nbins: int = 32, hmax: float = 0.5,
+              nslots: int = 3, nchunks: int = 64, shared_design: bool = False):
+    """Binned semivariogram features of nsets data sets (see vecchia_variogram).
+    locs: (nsets, k, 2) or (k, 2) with shared_design; y: (nsets, k).  Returns
+    (features float32 (nsets, nslots*nbins), gamma float64 (nsets, nbins))."""
+    _dev_check(locs, y, nu_slot)
+    nsets, k = y.shape
+    lib = L.lib()
+    ws = torch.empty(int(lib.vecchia_variogram_workspace_size(nsets, nbins, nchunks)), dtype=torch.uint8,
+                     device=y.device)
+    feat = torch.empty((nsets, nslots * nbins), dtype=torch.float32, device=y.device)
+    gam = torch.empty((nsets, nbins), dtype=torch.float64, device=y.device)
+    stride = 0 if shared_design else k * 2
+    L.check(lib.vecchia_variogram(_p(locs), stride, _p(y), k, nsets, k, nbins, hmax, _p(nu_slot), nslots, _p(feat),
+                                  _p(gam), nchunks, _p(ws), ws.numel(), _stream(y.device)), "vecchia_variogram")
+    return feat, gam
+
+
+def gemm(A: torch.Tensor, B: torch.Tensor, C: torch.Tensor, *, ta: bool = False, tb: bool = False, bias=None,
+         mask=None, Z=None, relu: bool = False, accumulate: bool = False, bf16: bool = True) -> torch.Tensor:
+    """C = op(A) op(B) (+bias) with the epilogues of vecchia_gemm."""
+    _dev_check(A, B, C, bias, mask, Z)
+    M = A.shape[1] if ta else A.shape[0]
+    K = A.shape[0] if ta else A.shape[1]
+    N = B.shape[0] if tb else B.shape[1]
+    L.check(L.lib().vecchia_gemm(_p(A), _p(B), _p(C), _p(bias), _p(mask), _p(Z), M, N, K, A.shape[1], B.shape[1],
+                                 C.shape[1], int(ta), int(tb), int(relu), int(accumulate), int(bf16),
+                                 _stream(A.device)), "vecchia_gemm")
+    return C
+
+
+def mse(out: torch.Tensor, target: torch.Tensor, dout: torch.Tensor, nparts: int = 8):
+    _dev_check(out, target, dout)
+    part = torch.empty(nparts, dtype=torch.float64, device=out.device)
+    L.check(L.lib().vecchia_mse(_p(out), _p(target), out.numel(), _p(dout), _p(part), nparts, _stream(out.device)),
+            "vecchia_mse")
+    return part
+
+
+def colsum(X: torch.Tensor, out: torch.Tensor) -> torch.Tensor:
+    _dev_check(X, out)
+    L.check(L.lib().vecchia_colsum(_p(X), X.shape[0], X.shape[1], X.shape[1], _p(out), _stream(X.device)),
+            "vecchia_colsum")
+    return out
+
+
+def adam(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tensor, step: int, lr: float = 1e-3,
+         beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+    _dev_check(param, grad, m, v)
+    L.check(L.lib().vecchia_adam(_p(param), _p(grad), _p(m), _p(v), param.numel(), lr, beta1, beta2, eps, step,
+                                 _stream(param.device)), "vecchia_adam")

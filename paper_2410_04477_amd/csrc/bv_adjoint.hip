@@ -256,10 +256,10 @@ bv_adj_kernel(AdjArgs a, ThetaPack thp) {
     if (MODE == 1) {
       // conditional-mean weights and variance of the last point given the others
       const double al = (double)X[(p - 1) * ldx];
-      for (int j = tid; j < m; j += NT) a.coef[n0 + j] = -(double)X[j * ldx] / al;
+      for (int j = tid; j < m; j += NT) a.coef[(size_t)tt * a.coef_stride + n0 + j] = -(double)X[j * ldx] / al;
       if (tid == 0) {
-        a.cvar[b] = 1.0 / al;
-        a.flag[b] = flag;
+        a.cvar[(size_t)tt * a.bc + b] = 1.0 / al;
+        a.flag[(size_t)tt * a.bc + b] = flag;
       }
       continue;
     }

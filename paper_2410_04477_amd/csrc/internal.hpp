@@ -45,8 +45,9 @@ struct AdjArgs {
   double* partial;       // [theta * bc + block]
   double* gpart;         // [(theta * bc + block) * 3 + k]
   int* flag;
-  double* coef;          // coefficient mode: conditional-mean weights, CSR like nbr_idx
-  double* cvar;          // coefficient mode: conditional variance per block
+  double* coef;          // coefficient mode: conditional-mean weights, CSR like nbr_idx, one copy per theta
+  double* cvar;          // coefficient mode: conditional variance per block and theta
+  int64_t coef_stride;   // coefficient mode: entries per theta (nbr_ptr[bc])
 };
 
 hipError_t launch_adjoint(int cfg, bool fp32, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);

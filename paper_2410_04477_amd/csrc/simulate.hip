@@ -18,22 +18,28 @@ __global__ void unit_blocks_kernel(int* __restrict__ bp, int n) {
   if (i <= n) bp[i] = i;
 }
 
+// grid.y runs over the data sets that share the design (same neighbour lists)
 __global__ void sim_pass_kernel(const int* __restrict__ nbr_ptr, const int* __restrict__ nbr_idx,
-                                const double* __restrict__ coef, const double* __restrict__ cvar,
+                                const double* __restrict__ coef, int64_t coef_stride, const double* __restrict__ cvar,
                                 const double* __restrict__ z, double* __restrict__ y, int* __restrict__ done, int n,
                                 int pass, int* __restrict__ ndone) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n || done[i] != 0) return;
+  const int t = blockIdx.y;
+  if (i >= n) return;
+  int* dn = done + (size_t)t * (n + 8);
+  if (dn[i] != 0) return;
   const int o0 = nbr_ptr[i], o1 = nbr_ptr[i + 1];
+  const double* cf = coef + (size_t)t * coef_stride;
+  const double* yy = y + (size_t)t * n;
   double acc = 0.0;
   for (int q = o0; q < o1; ++q) {
     const int j = nbr_idx[q];
-    const int dj = done[j];
+    const int dj = dn[j];
     if (dj == 0 || dj >= pass) return;  // a neighbour is not drawn yet
-    acc += coef[q] * y[j];
+    acc += cf[q] * yy[j];
   }
-  y[i] = acc + sqrt(cvar[i]) * z[i];
-  done[i] = pass;
+  y[(size_t)t * n + i] = acc + sqrt(cvar[(size_t)t * n + i]) * z[(size_t)t * n + i];
+  dn[i] = pass;
   atomicAdd(ndone, 1);
 }
 
@@ -46,7 +52,7 @@ inline size_t al256s(size_t x) { return (x + 255) & ~(size_t)255; }
 struct SimLayout {
   size_t bp, cfg, sched, counts, stats, coef, cvar, flag, done, total;
 };
-SimLayout sim_layout(int64_t n, int64_t nnz) {
+SimLayout sim_layout(int64_t n, int64_t nnz, int64_t nt) {
   SimLayout L;
   size_t o = 0;
   L.bp = o;     o = al256s(o + sizeof(int) * (n + 1));
@@ -54,10 +60,10 @@ SimLayout sim_layout(int64_t n, int64_t nnz) {
   L.sched = o;  o = al256s(o + sizeof(int) * n);
   L.counts = o; o = al256s(o + sizeof(int) * 64);
   L.stats = o;  o = al256s(o + sizeof(unsigned long long) * 8 + sizeof(int) * 16);
-  L.coef = o;   o = al256s(o + sizeof(double) * (nnz > 0 ? nnz : 1));
-  L.cvar = o;   o = al256s(o + sizeof(double) * n);
-  L.flag = o;   o = al256s(o + sizeof(int) * n);
-  L.done = o;   o = al256s(o + sizeof(int) * (n + 8));
+  L.coef = o;   o = al256s(o + sizeof(double) * (nnz > 0 ? nnz : 1) * nt);
+  L.cvar = o;   o = al256s(o + sizeof(double) * n * nt);
+  L.flag = o;   o = al256s(o + sizeof(int) * n * nt);
+  L.done = o;   o = al256s(o + sizeof(int) * (n + 8) * nt + 64);
   L.total = o;
   return L;
 }
@@ -70,28 +76,30 @@ template <typename P> P* at(void* base, size_t off) { return reinterpret_cast<P*
     if (e_ != hipSuccess) return VECCHIA_EHIP; \
   } while (0)
 
-extern "C" size_t vecchia_simulate_workspace_size(int64_t n, int64_t nnz) {
-  if (n <= 0 || nnz < 0) return 0;
-  return sim_layout(n, nnz).total;
+extern "C" size_t vecchia_simulate_workspace_size(int64_t n, int64_t nnz, int32_t ntheta) {
+  if (n <= 0 || nnz < 0 || ntheta <= 0) return 0;
+  return sim_layout(n, nnz, ntheta).total;
 }
 
 extern "C" int vecchia_simulate(const double* locs_ord, int64_t n, int32_t d, const int32_t* nbr_ptr,
-                                const int32_t* nbr_idx, const vecchia_theta* theta, const double* z, double* y,
-                                void* workspace, size_t ws_bytes, void* stream) {
+                                const int32_t* nbr_idx, const vecchia_theta* theta, int32_t ntheta, const double* z,
+                                double* y, void* workspace, size_t ws_bytes, void* stream) {
   if (!locs_ord || !nbr_ptr || !nbr_idx || !theta || !z || !y || !workspace) return VECCHIA_EINVAL;
   if (n <= 0 || d < 1 || d > 3 || n >= ((int64_t)1 << 31)) return VECCHIA_EINVAL;
+  if (ntheta < 1 || ntheta > kMaxThetaPerLaunch || (int64_t)ntheta * (n + 8) >= ((int64_t)1 << 31))
+    return VECCHIA_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   int hnnz = 0;
   SCHECK(hipMemcpyAsync(&hnnz, nbr_ptr + n, sizeof(int), hipMemcpyDeviceToHost, s));
   SCHECK(hipStreamSynchronize(s));
-  const SimLayout L = sim_layout(n, hnnz);
+  const SimLayout L = sim_layout(n, hnnz, ntheta);
   if (ws_bytes < L.total) return VECCHIA_ENOMEM;
   ThetaPack thp;
   memset(&thp, 0, sizeof(thp));
-  {
-    const vecchia_theta& t = *theta;
+  for (int q = 0; q < ntheta; ++q) {
+    const vecchia_theta& t = theta[q];
     if (!(t.sigma2 > 0) || !(t.range > 0) || !(t.nugget >= 0)) return VECCHIA_EINVAL;
-    ThetaDev& o = thp.t[0];
+    ThetaDev& o = thp.t[q];
     if (t.nu == 0.5) o.nu_code = 0;
     else if (t.nu == 1.5) o.nu_code = 1;
     else if (t.nu == 2.5) o.nu_code = 2;
@@ -132,8 +140,9 @@ extern "C" int vecchia_simulate(const double* locs_ord, int64_t n, int32_t d, co
   a.block_ptr = bp;
   a.nbr_ptr = nbr_ptr;
   a.nbr_idx = nbr_idx;
-  a.ntheta = 1;
+  a.ntheta = ntheta;
   a.bc = ni;
+  a.coef_stride = hnnz;
   a.d = d;
   a.ldx = 1;
   a.flag = at<int>(workspace, L.flag);
@@ -143,17 +152,18 @@ extern "C" int vecchia_simulate(const double* locs_ord, int64_t n, int32_t d, co
     if (hc[c] == 0) continue;
     a.sched = sched + hoff[c];
     a.nsched = hc[c];
-    SCHECK(launch_coefficients(c, a, thp, hc[c], s));
+    SCHECK(launch_coefficients(c, a, thp, hc[c] * ntheta, s));
   }
   // recursion in passes
   int* done = at<int>(workspace, L.done);
-  int* ndone = done + n + 4;
-  SCHECK(launch_fill_int(done, ni + 8, 0, s));
+  int* ndone = done + (size_t)(n + 8) * ntheta;
+  SCHECK(launch_fill_int(done, (ni + 8) * ntheta + 8, 0, s));
+  const int target = ni * ntheta;
   int total = 0;
-  for (int pass = 1; total < ni; pass += 16) {
+  for (int pass = 1; total < target; pass += 16) {
     for (int q = 0; q < 16; ++q)
-      hipLaunchKernelGGL(sim_pass_kernel, dim3((ni + 255) / 256), dim3(256), 0, s, nbr_ptr, nbr_idx, a.coef, a.cvar,
-                         z, y, done, ni, pass + q, ndone);
+      hipLaunchKernelGGL(sim_pass_kernel, dim3((ni + 255) / 256, ntheta), dim3(256), 0, s, nbr_ptr, nbr_idx, a.coef,
+                         (int64_t)hnnz, a.cvar, z, y, done, ni, pass + q, ndone);
     SCHECK(hipGetLastError());
     int prev = total;
     SCHECK(hipMemcpyAsync(&total, ndone, sizeof(int), hipMemcpyDeviceToHost, s));

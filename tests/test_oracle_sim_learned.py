@@ -79,3 +79,15 @@ def test_c_block_simulator_matches_sequential_vecchia():
     ptr, idx = point_neighbors(s[order], m)
     ys = coracle.simulate(s[order], np.arange(n + 1), ptr, idx, th, z)
     np.testing.assert_allclose(ys, ref[order], rtol=1e-10, atol=1e-12)
+
+
+def test_bf16_round_matches_format():
+    # exactly representable values are unchanged; halfway cases go to even
+    assert LR.bf16_round([1.0, -2.5, 0.0])[1] == -2.5
+    one_ulp = 2.0 ** -7
+    assert LR.bf16_round([1.0 + one_ulp / 2])[0] == 1.0                 # tie -> even (1.0)
+    assert LR.bf16_round([1.0 + 3 * one_ulp / 2])[0] == 1.0 + 2 * one_ulp  # tie -> even
+    assert LR.bf16_round([1.0 + 0.6 * one_ulp])[0] == 1.0 + one_ulp
+    x = W.rng(3).standard_normal(1000)
+    r = LR.bf16_round(x)
+    assert np.all(np.abs(r - x) <= np.abs(x) * 2.0 ** -8 * 1.0001)
