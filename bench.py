@@ -37,7 +37,7 @@ def log(msg: str) -> None:
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("bv_adjoint.hip", "bv_forward.hip", "common.hpp"):
+    for f in ("bv_mfma.hip", "bv_adjoint.hip", "bv_forward.hip", "common.hpp"):
         with open(os.path.join(ROOT, "paper_2410_04477_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -56,6 +56,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C3")
+    ap.add_argument("--engine", default="mfma", choices=["mfma", "tiles"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -98,7 +99,8 @@ def main() -> int:
     log(f"preprocessing: bc={w.bc}, m={w.m}")
     t1 = time.perf_counter()
     model = BlockVecchia(locs, y, w.bc, w.m, th0.nu, W.kmeans_init(w.n, w.bc, w.seed_kmeans),
-                         W.block_permutation(w.bc, w.seed_kmeans), th0.aniso[: w.d], w.kmeans_iters)
+                         W.block_permutation(w.bc, w.seed_kmeans), th0.aniso[: w.d], w.kmeans_iters,
+                         engine=args.engine)
     torch.cuda.synchronize()
     t_pre = time.perf_counter() - t1
     plan = model.plan
@@ -155,18 +157,19 @@ def main() -> int:
                                            lsz[blk].astype(np.float64))))
     avg_launch_s = ms_dom / n_dom / 1e3
     achieved = flops_launch / avg_launch_s
-    R, G = api.tile_config(cfg_dom)
+    R, G = api.tile_config(cfg_dom, plan.engine)
+    kname = (f"bv_mfma_kernel<float,{G},1>" if plan.engine == "mfma" else f"bv_adj_kernel<float,{R},{G},0>")
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tr = json.load(fh)
-        ent = tr.get(f"bv_adj_kernel<float,{R},{G}>")
+        ent = tr.get(kname)
         if ent and tr.get("kernel_source_sha") == kernel_source_sha():
             traffic = ent.get("bytes_per_launch")
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
                 "frac": achieved / FP32_VECTOR_PEAK, "traffic": traffic,
-                "kernel": f"bv_adj_kernel<float,{R},{G}>", "blocks_per_launch": int(blk.size),
+                "kernel": kname, "blocks_per_launch": int(blk.size),
                 "avg_launch_ms": avg_launch_s * 1e3, "flops_per_launch": flops_launch,
                 "share_of_step": ms_dom / (1e3 * gpu_s) if gpu_s > 0 else None}
     total_flops_step = float(np.sum(step_flops(psz.astype(np.float64), msz.astype(np.float64),
@@ -216,7 +219,7 @@ def main() -> int:
                                f"bc={w.bc}, m={w.m}, y by sequential Vecchia ({w.sim_m} nbrs)",
                    "step": "loglik + adjoint gradient (sigma2, range, nugget)",
                    "precision": "fp32-bulk, fp64 accumulation and guard re-factorisation",
-                   "n": w.n, "bc": int(plan.bc), "m": w.m},
+                   "n": w.n, "bc": int(plan.bc), "m": w.m, "engine": args.engine},
         "points_per_s": evals * w.n,
         "gflops_per_step": total_flops_step / 1e9,
         "roofline": roofline,

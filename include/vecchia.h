@@ -128,19 +128,36 @@ int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const doubl
                       int32_t* nbr_ptr, int32_t* nbr_idx, int64_t nbr_cap,
                       void* workspace, size_t ws_bytes, void* stream);
 
+/* Kernel families.
+ * VECCHIA_ENGINE_MFMA (default): each block's bordered joint matrix lives in
+ *   16 x 16 matrix-core accumulator tiles of ONE wave (a 64-thread workgroup).
+ *   The Cholesky runs in panels of four columns with rank-4 MFMA updates; the
+ *   adjoint's back-substitution and contraction are MFMA products, 32
+ *   right-hand sides per pass, so any l_i fits the LDS.  FP64 classes above
+ *   G = 8 tile rows exceed the register file and spill part of the tiles.
+ * VECCHIA_ENGINE_MFMA_WG: the same tiles spread over the four waves of a
+ *   workgroup, for every size class (two barriers per panel).
+ * VECCHIA_ENGINE_TILES: one register tile per thread, one barrier per column
+ *   (vector ALU only). */
+typedef enum { VECCHIA_ENGINE_MFMA = 0, VECCHIA_ENGINE_TILES = 1, VECCHIA_ENGINE_MFMA_WG = 2 } vecchia_engine;
+
 /* ------------------------------------------------------------------ plan --
  * Launch schedule for one (block_ptr, nbr_ptr) pair: blocks are grouped into
- * size classes by p_i = m_i + l_i so that each class runs the register-tile
+ * size classes by p_i = m_i + l_i so that each class runs the kernel
  * configuration that fits it.  Build once per data set, reuse for every
  * likelihood evaluation.  The struct is host memory owned by the caller; its
  * device arrays live in the caller's workspace, which must stay allocated
  * while the plan is used.  Synchronises `stream`.
  *   max_theta    largest ntheta that later calls will pass
  *   workspace    >= vecchia_plan_workspace_size(bc, max_theta) bytes
- * Returns VECCHIA_EUNSUPPORTED if some block has m_i + l_i above
- * VECCHIA_MAX_JOINT (use smaller m, or smaller blocks). */
+ * Blocks with m_i + l_i above VECCHIA_MAX_JOINT (up to 16383) form a size class
+ * of their own: each is generated into a global workspace and factored
+ * left-looking in 16-column panels with MFMA panel updates.  They need a
+ * second workspace of plan->large_ws_bytes, attached with
+ * vecchia_plan_attach_large before the first evaluation; vecchia_loglik_grad
+ * returns VECCHIA_EUNSUPPORTED for them. */
 #define VECCHIA_MAX_BUCKETS 24
-#define VECCHIA_MAX_JOINT 176
+#define VECCHIA_MAX_JOINT 175  /* largest m_i + l_i (both engines) */
 typedef struct {
   int64_t n, bc;
   int32_t max_theta;
@@ -155,16 +172,26 @@ typedef struct {
   size_t ws_bytes;
   size_t off_sched, off_partial, off_flag, off_list, off_count, off_chunk, off_grad;
   void* timing;   /* NULL unless vecchia_plan_set_timing enabled per-launch timing */
+  int32_t engine; /* vecchia_engine of the kernels this plan schedules */
+  int64_t nlarge;            /* blocks with m_i + l_i > VECCHIA_MAX_JOINT */
+  size_t large_ws_bytes;     /* workspace they need (vecchia_plan_attach_large) */
+  int32_t large_slots;       /* blocks factored concurrently */
+  int64_t large_slot_elems;  /* elements per slot */
+  void* large_ws;
+  int32_t bucket_lmax[VECCHIA_MAX_BUCKETS];  /* largest l_i of each class */
+  int32_t lds_bytes;                          /* device LDS limit per workgroup */
 } vecchia_plan;
 
 size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
-/* Register-tile configuration of a size class (plan->bucket_cfg[q]): tile
- * size R and tile-grid order G, joint capacity R*G.  Returns VECCHIA_EINVAL for
- * an unknown configuration. */
-int vecchia_tile_config(int32_t cfg, int32_t* R, int32_t* G);
+/* Tile configuration of a size class (plan->bucket_cfg[q]) of an engine: tile
+ * size R and tile-grid order G (joint capacity R*G; the matrix-core engine has
+ * R = 16 and holds the bordered matrix, p + 1 <= 16 G).  VECCHIA_EINVAL for an
+ * unknown configuration. */
+int vecchia_tile_config(int32_t engine, int32_t cfg, int32_t* R, int32_t* G);
 int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, const int32_t* nbr_ptr,
-                      int64_t n, int64_t bc, int32_t max_theta,
+                      int64_t n, int64_t bc, int32_t max_theta, int32_t engine,
                       void* workspace, size_t ws_bytes, void* stream);
+int vecchia_plan_attach_large(vecchia_plan* plan, void* large_workspace, size_t bytes);
 
 /* Per-launch timing for benchmarks.  When enabled, vecchia_loglik and
  * vecchia_loglik_grad bracket every size-class kernel launch with hipEvents

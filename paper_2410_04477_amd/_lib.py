@@ -10,7 +10,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libvecchia.so")
 
 MAX_BUCKETS = 24
-MAX_JOINT = 176
+MAX_JOINT = 175
+ENGINE_MFMA, ENGINE_TILES, ENGINE_MFMA_WG = 0, 1, 2
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, FP32_BULK = 0, 1
@@ -30,7 +31,10 @@ class Plan(ctypes.Structure):
                 ("ws", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t),
                 ("off_sched", ctypes.c_size_t), ("off_partial", ctypes.c_size_t), ("off_flag", ctypes.c_size_t),
                 ("off_list", ctypes.c_size_t), ("off_count", ctypes.c_size_t), ("off_chunk", ctypes.c_size_t),
-                ("off_grad", ctypes.c_size_t), ("timing", ctypes.c_void_p)]
+                ("off_grad", ctypes.c_size_t), ("timing", ctypes.c_void_p), ("engine", ctypes.c_int32),
+                ("nlarge", ctypes.c_int64), ("large_ws_bytes", ctypes.c_size_t), ("large_slots", ctypes.c_int32),
+                ("large_slot_elems", ctypes.c_int64), ("large_ws", ctypes.c_void_p),
+                ("bucket_lmax", ctypes.c_int32 * MAX_BUCKETS), ("lds_bytes", ctypes.c_int32)]
 
 
 class VecchiaError(RuntimeError):
@@ -49,7 +53,7 @@ SIGNATURES = {
     "vecchia_neighbors_workspace_size": (SZ, [I64, I64, I32, I32]),
     "vecchia_neighbors": (ctypes.c_int, [P, I64, I32, P, P, I64, I32, P, P, I64, P, SZ, P]),
     "vecchia_plan_workspace_size": (SZ, [I64, I32]),
-    "vecchia_plan_init": (ctypes.c_int, [P, P, P, I64, I64, I32, P, SZ, P]),
+    "vecchia_plan_init": (ctypes.c_int, [P, P, P, I64, I64, I32, I32, P, SZ, P]),
     "vecchia_loglik": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P]),
     "vecchia_permute": (ctypes.c_int, [P, I64, I32, P, P, P]),
     "vecchia_loglik_grad": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P, P, P]),
@@ -61,7 +65,8 @@ SIGNATURES = {
     "vecchia_mse": (ctypes.c_int, [P, P, I32, P, P, I32, P]),
     "vecchia_colsum": (ctypes.c_int, [P, I32, I32, I32, P, P]),
     "vecchia_adam": (ctypes.c_int, [P, P, P, P, I64, D, D, D, D, I64, P]),
-    "vecchia_tile_config": (ctypes.c_int, [I32, P, P]),
+    "vecchia_tile_config": (ctypes.c_int, [I32, I32, P, P]),
+    "vecchia_plan_attach_large": (ctypes.c_int, [P, P, SZ]),
     "vecchia_plan_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
     "vecchia_plan_timing": (ctypes.c_int, [P, P, P, ctypes.c_int]),
 }

@@ -49,10 +49,14 @@ def make_theta(th) -> L.Theta:
     return L.Theta(float(s2), float(rg), float(nug), float(nu), (ctypes.c_double * 3)(*an))
 
 
-def tile_config(cfg: int):
+ENGINES = {"mfma": L.ENGINE_MFMA, "tiles": L.ENGINE_TILES, "mfma_wg": L.ENGINE_MFMA_WG}
+
+
+def tile_config(cfg: int, engine: str = "mfma"):
     """(R, G) of a size-class configuration."""
     r, g = ctypes.c_int32(0), ctypes.c_int32(0)
-    L.check(L.lib().vecchia_tile_config(cfg, ctypes.byref(r), ctypes.byref(g)), "vecchia_tile_config")
+    L.check(L.lib().vecchia_tile_config(ENGINES[engine], cfg, ctypes.byref(r), ctypes.byref(g)),
+            "vecchia_tile_config")
     return r.value, g.value
 
 
@@ -107,7 +111,8 @@ def neighbors(locs_perm: torch.Tensor, block_ptr: torch.Tensor, m: int,
 class Plan:
     """Launch schedule for one block / neighbour structure (vecchia_plan_init)."""
 
-    def __init__(self, block_ptr: torch.Tensor, nbr_ptr: torch.Tensor, n: int, max_theta: int = 1):
+    def __init__(self, block_ptr: torch.Tensor, nbr_ptr: torch.Tensor, n: int, max_theta: int = 1,
+                 engine: str = "mfma"):
         _dev_check(block_ptr, nbr_ptr)
         if block_ptr.dtype != torch.int32 or nbr_ptr.dtype != torch.int32:
             raise ValueError("block_ptr / nbr_ptr must be int32")
@@ -117,8 +122,14 @@ class Plan:
                               device=block_ptr.device)
         self.c = L.Plan()
         L.check(lib.vecchia_plan_init(ctypes.byref(self.c), _p(block_ptr), _p(nbr_ptr), n, bc, max_theta,
-                                      _p(self.ws), self.ws.numel(), _stream(block_ptr.device)),
+                                      ENGINES[engine], _p(self.ws), self.ws.numel(), _stream(block_ptr.device)),
                 "vecchia_plan_init")
+        self.engine = engine
+        self.large_ws = None
+        if self.c.nlarge > 0:
+            self.large_ws = torch.empty(int(self.c.large_ws_bytes), dtype=torch.uint8, device=block_ptr.device)
+            L.check(lib.vecchia_plan_attach_large(ctypes.byref(self.c), _p(self.large_ws), self.large_ws.numel()),
+                    "vecchia_plan_attach_large")
         self.block_ptr, self.nbr_ptr = block_ptr, nbr_ptr
 
     @property

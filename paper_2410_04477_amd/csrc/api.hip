@@ -79,8 +79,15 @@ bool theta_to_dev(const vecchia_theta& t, int d, ThetaDev& o) {
 template <typename P> P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(base) + off); }
 }  // namespace
 
-extern "C" int vecchia_tile_config(int32_t cfg, int32_t* R, int32_t* G) {
-  if (cfg < 0 || cfg >= kNumCfgs || !R || !G) return VECCHIA_EINVAL;
+extern "C" int vecchia_tile_config(int32_t engine, int32_t cfg, int32_t* R, int32_t* G) {
+  if (!R || !G) return VECCHIA_EINVAL;
+  if (engine == kEngineMfma || engine == kEngineMfmaWg) {
+    if (cfg < 0 || cfg >= kMfmaMaxG) return VECCHIA_EINVAL;
+    *R = 16;
+    *G = cfg + 1;
+    return VECCHIA_OK;
+  }
+  if (engine != kEngineTiles || cfg < 0 || cfg >= kNumCfgs) return VECCHIA_EINVAL;
   *R = kCfgs[cfg].R;
   *G = kCfgs[cfg].G;
   return VECCHIA_OK;
@@ -92,10 +99,12 @@ extern "C" size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta) {
 }
 
 extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, const int32_t* nbr_ptr, int64_t n,
-                                 int64_t bc, int32_t max_theta, void* workspace, size_t ws_bytes, void* stream) {
+                                 int64_t bc, int32_t max_theta, int32_t engine, void* workspace, size_t ws_bytes,
+                                 void* stream) {
   if (!plan || !block_ptr || !nbr_ptr || !workspace || n <= 0 || bc <= 0 || bc > n || max_theta <= 0 ||
       n >= (int64_t)1 << 31 || (int64_t)bc * max_theta >= (int64_t)1 << 31)
     return VECCHIA_EINVAL;
+  if (engine != kEngineMfma && engine != kEngineTiles && engine != kEngineMfmaWg) return VECCHIA_EINVAL;
   const PlanLayout L = plan_layout(bc, max_theta);
   if (ws_bytes < L.total) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
@@ -104,35 +113,55 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   int* counts = at<int>(workspace, L.count);            // [0..32) counts, [32..64) cursors/offsets
   unsigned long long* stats = at<unsigned long long>(workspace, L.chunk);
   int* maxes = at<int>(workspace, L.chunk + 128);
+  int* lmax_cfg = at<int>(workspace, L.chunk + 256);    // [0..32) largest l_i per configuration
   VCHECK_HIP(launch_fill_int(counts, 64, 0, s));
   VCHECK_HIP(launch_fill_int(maxes, 16, 0, s));
+  VCHECK_HIP(launch_fill_int(lmax_cfg, 32, 0, s));
   VCHECK_HIP(launch_fill_int(reinterpret_cast<int*>(stats), 16, 0, s));
-  VCHECK_HIP(launch_classify(block_ptr, nbr_ptr, (int)bc, cfg_of, counts, stats, maxes, s));
+  VCHECK_HIP(launch_classify(block_ptr, nbr_ptr, (int)bc, cfg_of, counts, stats, maxes, lmax_cfg, engine, s));
   int hcounts[32];
   int hmax[4];
+  int hlmax[32];
   unsigned long long hstats[4];
   VCHECK_HIP(hipMemcpyAsync(hcounts, counts, sizeof(hcounts), hipMemcpyDeviceToHost, s));
   VCHECK_HIP(hipMemcpyAsync(hmax, maxes, sizeof(hmax), hipMemcpyDeviceToHost, s));
+  VCHECK_HIP(hipMemcpyAsync(hlmax, lmax_cfg, sizeof(hlmax), hipMemcpyDeviceToHost, s));
   VCHECK_HIP(hipMemcpyAsync(hstats, stats, sizeof(hstats), hipMemcpyDeviceToHost, s));
   VCHECK_HIP(hipStreamSynchronize(s));
   if (hmax[3] > 0) {
-    // a block with no points, or with m_i + l_i above the largest tile configuration
-    return hmax[0] > VECCHIA_MAX_JOINT ? VECCHIA_EUNSUPPORTED : VECCHIA_EINVAL;
+    // a block with no points, or larger than even the global-workspace kernel takes
+    return hmax[0] > 16383 ? VECCHIA_EUNSUPPORTED : VECCHIA_EINVAL;
   }
-  int hoff[32];
+  int hoff[32] = {0};
   int acc = 0, nb = 0;
-  for (int c = 0; c < kNumCfgs; ++c) {
+  const int ncfg = engine == kEngineTiles ? kNumCfgs : kMfmaMaxG;
+  for (int c = 0; c < ncfg; ++c) {
     hoff[c] = acc;
     if (hcounts[c] > 0) {
       plan->bucket_cfg[nb] = c;
       plan->bucket_off[nb] = acc;
+      plan->bucket_lmax[nb] = hlmax[c];
       ++nb;
     }
     acc += hcounts[c];
   }
+  plan->nlarge = hcounts[kLargeCfg];
+  if (plan->nlarge > 0) {
+    hoff[kLargeCfg] = acc;
+    plan->bucket_cfg[nb] = kLargeCfg;
+    plan->bucket_off[nb] = acc;
+    plan->bucket_lmax[nb] = hlmax[kLargeCfg];
+    ++nb;
+    acc += hcounts[kLargeCfg];
+    const int64_t P = 16 * (int64_t)((hmax[0] + 1 + 15) / 16);
+    const int64_t work = plan->nlarge * (int64_t)max_theta;
+    plan->large_slots = (int32_t)(work < 256 ? work : 256);
+    plan->large_slot_elems = P * P;
+    plan->large_ws_bytes = (size_t)plan->large_slots * (size_t)(P * P) * sizeof(double);
+  }
   plan->bucket_off[nb] = acc;
   plan->nbuckets = nb;
-  VCHECK_HIP(hipMemcpyAsync(counts + 32, hoff, sizeof(int) * kNumCfgs, hipMemcpyHostToDevice, s));
+  VCHECK_HIP(hipMemcpyAsync(counts + 32, hoff, sizeof(int) * 32, hipMemcpyHostToDevice, s));
   VCHECK_HIP(launch_fill_int(counts, 32, 0, s));
   VCHECK_HIP(launch_scatter(cfg_of, (int)bc, counts + 32, counts, at<int>(workspace, L.sched), s));
   VCHECK_HIP(hipStreamSynchronize(s));
@@ -154,8 +183,69 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   plan->off_count = L.count;
   plan->off_chunk = L.chunk;
   plan->off_grad = L.grad;
+  plan->engine = engine;
+  int dev = 0, lds = 0;
+  VCHECK_HIP(hipGetDevice(&dev));
+  VCHECK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+  plan->lds_bytes = lds;
   return VECCHIA_OK;
 }
+
+// Forward arguments in the form the matrix-core kernels take.
+static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
+  AdjArgs a;
+  memset(&a, 0, sizeof(a));
+  a.locs = f.locs;
+  a.y = f.y;
+  a.block_ptr = f.block_ptr;
+  a.nbr_ptr = f.nbr_ptr;
+  a.nbr_idx = f.nbr_idx;
+  a.sched = f.sched;
+  a.list = f.list;
+  a.list_count = f.list_count;
+  a.nsched = f.nsched;
+  a.ntheta = f.ntheta;
+  a.bc = f.bc;
+  a.d = f.d;
+  a.fp32_guard = f.fp32_guard;
+  a.flag_or = f.flag_or;
+  a.ldx = 0;   // set per size class
+  a.partial = f.partial;
+  a.flag = f.flag;
+  return a;
+}
+
+// Matrix-core kernel of size class q: the one-wave kernels where the class
+// fits them (engine MFMA), else the four-wave kernels.  mode 0: value,
+// 1: value + gradient.  VECCHIA_EUNSUPPORTED when the four-wave adjoint's
+// right-hand sides do not fit the device LDS.
+static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mode, AdjArgs a, const ThetaPack& thp,
+                             int grid, hipStream_t s) {
+  const int g = plan->bucket_cfg[q] + 1;
+  if (plan->engine == kEngineMfma && wave_fits(g, fp32)) {
+    VCHECK_HIP(launch_wave(g, fp32, mode, a, thp, grid, s));
+    return VECCHIA_OK;
+  }
+  a.ldx = mfma_ldx(plan->bucket_lmax[q] + 2);
+  if (mfma_lds_need(g, fp32, mode, a.ldx) > (size_t)plan->lds_bytes) return VECCHIA_EUNSUPPORTED;
+  VCHECK_HIP(launch_mfma(g, fp32, mode, a, thp, grid, s));
+  return VECCHIA_OK;
+}
+
+// Vector-ALU adjoint of size class q (right-hand sides held whole in LDS).
+static int launch_tiles_adjoint(const vecchia_plan* plan, int q, bool fp32, AdjArgs a, const ThetaPack& thp,
+                                int grid, hipStream_t s) {
+  a.ldx = plan->bucket_lmax[q] + 2;
+  if (adjoint_lds_need(plan->bucket_cfg[q], fp32, a.ldx) > (size_t)plan->lds_bytes) return VECCHIA_EUNSUPPORTED;
+  VCHECK_HIP(launch_adjoint(plan->bucket_cfg[q], fp32, a, thp, grid, s));
+  return VECCHIA_OK;
+}
+
+#define VCHECK_ST(x)            \
+  do {                          \
+    int st_ = (x);              \
+    if (st_) return st_;        \
+  } while (0)
 
 // -------------------------------------------------------------- timing ----
 
@@ -221,6 +311,39 @@ extern "C" int vecchia_plan_timing(vecchia_plan* plan, double* ms, int64_t* laun
   return VECCHIA_OK;
 }
 
+extern "C" int vecchia_plan_attach_large(vecchia_plan* plan, void* large_workspace, size_t bytes) {
+  if (!plan) return VECCHIA_EINVAL;
+  if (plan->nlarge == 0) return VECCHIA_OK;
+  if (!large_workspace) return VECCHIA_EINVAL;
+  if (bytes < plan->large_ws_bytes) return VECCHIA_ENOMEM;
+  plan->large_ws = large_workspace;
+  return VECCHIA_OK;
+}
+
+static LargeArgs as_large(const FwdArgs& f, const vecchia_plan* plan) {
+  LargeArgs a;
+  memset(&a, 0, sizeof(a));
+  a.locs = f.locs;
+  a.y = f.y;
+  a.block_ptr = f.block_ptr;
+  a.nbr_ptr = f.nbr_ptr;
+  a.nbr_idx = f.nbr_idx;
+  a.sched = f.sched;
+  a.list = f.list;
+  a.list_count = f.list_count;
+  a.nsched = f.nsched;
+  a.ntheta = f.ntheta;
+  a.bc = f.bc;
+  a.d = f.d;
+  a.fp32_guard = f.fp32_guard;
+  a.flag_or = f.flag_or;
+  a.ws = plan->large_ws;
+  a.slot_elems = plan->large_slot_elems;
+  a.partial = f.partial;
+  a.flag = f.flag;
+  return a;
+}
+
 // -------------------------------------------------------------- loglik ----
 
 static int check_common(const vecchia_plan* plan, const double* locs, const double* y, int32_t d,
@@ -246,6 +369,7 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
   int st = check_common(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision);
   if (st) return st;
   if (!loglik) return VECCHIA_EINVAL;
+  if (plan->nlarge > 0 && !plan->large_ws) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const int bc = (int)plan->bc;
   void* ws = plan->ws;
@@ -280,7 +404,15 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
       a.nsched = ns;
       TimingRec tr;
       VCHECK_HIP(time_begin(plan, q, s, tr));
-      VCHECK_HIP(launch_forward(plan->bucket_cfg[q], fp32, a, thp, ns * nt, s));
+      if (plan->bucket_cfg[q] == kLargeCfg) {
+        const int g = ns * nt < plan->large_slots ? ns * nt : plan->large_slots;
+        VCHECK_HIP(launch_large(fp32, as_large(a, plan), thp, g, s));
+      } else {
+        if (plan->engine == kEngineTiles)
+          VCHECK_HIP(launch_forward(plan->bucket_cfg[q], fp32, a, thp, ns * nt, s));
+        else
+          VCHECK_ST(launch_mfma_class(plan, q, fp32, 0, as_adj(a, plan), thp, ns * nt, s));
+      }
       VCHECK_HIP(time_end(plan, s, tr));
     }
     if (fp32) {
@@ -299,7 +431,12 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
         r.list = list + plan->bucket_off[q] * nt;
         r.list_count = count + q;
         const int cap = ns * nt;
-        VCHECK_HIP(launch_forward(plan->bucket_cfg[q], false, r, thp, cap < 256 ? cap : 256, s));
+        if (plan->bucket_cfg[q] == kLargeCfg)
+          VCHECK_HIP(launch_large(false, as_large(r, plan), thp, cap < plan->large_slots ? cap : plan->large_slots, s));
+        else if (plan->engine == kEngineTiles)
+          VCHECK_HIP(launch_forward(plan->bucket_cfg[q], false, r, thp, cap < 256 ? cap : 256, s));
+        else
+          VCHECK_ST(launch_mfma_class(plan, q, false, 0, as_adj(r, plan), thp, cap, s));
       }
     }
     VCHECK_HIP(launch_reduce_partials(part, flag, bc, nt, fp32 ? 0 : 1, loglik + t0,
@@ -321,6 +458,7 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
   int st = check_common(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision);
   if (st) return st;
   if (!loglik || !grad) return VECCHIA_EINVAL;
+  if (plan->nlarge > 0) return VECCHIA_EUNSUPPORTED;  // gradient above the register capacity
   hipStream_t s = (hipStream_t)stream;
   const int bc = (int)plan->bc;
   void* ws = plan->ws;
@@ -348,7 +486,7 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
     a.bc = bc;
     a.d = d;
     a.fp32_guard = precision == VECCHIA_FP32_BULK_FORCE_REFACTOR ? 2 : (fp32 ? 1 : 0);
-    a.ldx = plan->lmax + 2;
+    a.ldx = 0;   // set per size class
     a.partial = part;
     a.gpart = gpart;
     a.flag = flag;
@@ -358,7 +496,10 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
       a.nsched = ns;
       TimingRec tr;
       VCHECK_HIP(time_begin(plan, q, s, tr));
-      VCHECK_HIP(launch_adjoint(plan->bucket_cfg[q], fp32, a, thp, ns * nt, s));
+      if (plan->engine == kEngineTiles)
+        VCHECK_ST(launch_tiles_adjoint(plan, q, fp32, a, thp, ns * nt, s));
+      else
+        VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, s));
       VCHECK_HIP(time_end(plan, s, tr));
     }
     if (fp32) {
@@ -376,7 +517,10 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
         r.list = list + plan->bucket_off[q] * nt;
         r.list_count = count + q;
         const int cap = ns * nt;
-        VCHECK_HIP(launch_adjoint(plan->bucket_cfg[q], false, r, thp, cap < 256 ? cap : 256, s));
+        if (plan->engine == kEngineTiles)
+          VCHECK_ST(launch_tiles_adjoint(plan, q, false, r, thp, cap < 256 ? cap : 256, s));
+        else
+          VCHECK_ST(launch_mfma_class(plan, q, false, 1, r, thp, cap, s));
       }
     }
     VCHECK_HIP(launch_reduce_partials(part, flag, bc, nt, fp32 ? 0 : 1, loglik + t0,

@@ -339,6 +339,13 @@ bv_adj_kernel(AdjArgs a, ThetaPack thp) {
   }
 }
 
+size_t adjoint_lds_need(int cfg, bool fp32, int ldx) {
+  const size_t R = kCfgs[cfg].R, G = kCfgs[cfg].G, P = R * G, e = fp32 ? 4 : 8;
+  const size_t nt = threads_for_grid((int)G);
+  // X (dynamic) + sidx, su, colbuf, pivbuf, ybuf, lrow, sred
+  return e * P * (size_t)ldx + 4 * P + e * (5 * P + 4 + R * P) + 8 * 3 * (nt / 64);
+}
+
 template <typename T, int C, int MODE>
 static hipError_t launch_adj_cfg(const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
   constexpr int R = kCfgs[C].R, G = kCfgs[C].G;

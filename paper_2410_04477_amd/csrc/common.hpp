@@ -43,6 +43,31 @@ __device__ __forceinline__ T matern_rho(T x, int nu_code) {
   return (T(1) + x + x * x * T(1.0 / 3.0)) * e;
 }
 
+// Branch-free closed forms: rho = e^-x (1 + c1 x + c2 x^2) with (c1, c2) =
+// (0, 0), (1, 0), (1, 1/3) for nu = 1/2, 3/2, 5/2, and
+// d rho / d range = (x / range) e^-x (g0 + g1 x + g2 x^2) with (g0, g1, g2) =
+// (1, 0, 0), (0, 1, 0), (0, 1/3, 1/3).
+template <typename T>
+struct MaternCoef {
+  T c1, c2, g0, g1, g2;
+  __device__ __forceinline__ explicit MaternCoef(int nu_code)
+      : c1(nu_code == 0 ? T(0) : T(1)),
+        c2(nu_code == 2 ? T(1.0 / 3.0) : T(0)),
+        g0(nu_code == 0 ? T(1) : T(0)),
+        g1(nu_code == 0 ? T(0) : (nu_code == 1 ? T(1) : T(1.0 / 3.0))),
+        g2(nu_code == 2 ? T(1.0 / 3.0) : T(0)) {}
+  __device__ __forceinline__ T rho(T x) const { return expneg<T>(x) * (T(1) + x * (c1 + c2 * x)); }
+  __device__ __forceinline__ void rho_drange(T x, T inv_range, T& r, T& dr) const {
+    const T e = expneg<T>(x);
+    r = e * (T(1) + x * (c1 + c2 * x));
+    dr = x * inv_range * e * (g0 + x * (g1 + g2 * x));
+  }
+};
+
+template <typename T> __device__ __forceinline__ T sqrt_fast(T x);
+template <> __device__ __forceinline__ double sqrt_fast<double>(double x) { return sqrt(x); }
+template <> __device__ __forceinline__ float sqrt_fast<float>(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 // rho and x * d rho / d x * (-1) / range, i.e. d rho(h/range) / d range.
 template <typename T>
 __device__ __forceinline__ void matern_rho_drange(T x, int nu_code, T inv_range, T& rho, T& drho) {
@@ -81,5 +106,15 @@ __host__ __device__ inline int cfg_for_joint(int p) {
     if (kCfgs[c].R * kCfgs[c].G >= p) return c;
   return -1;
 }
+
+// Matrix-core engine: 16 x 16 tiles, G tile rows for the bordered (p + 1)-row
+// matrix, G = 1..kMfmaMaxG; configuration id = G - 1.
+constexpr int kMfmaMaxG = 11;
+__host__ __device__ inline int cfg_mfma_for_joint(int p) {
+  const int g = (p + 1 + 15) / 16;
+  return (g >= 1 && g <= kMfmaMaxG) ? g - 1 : -1;
+}
+
+enum { kEngineMfma = 0, kEngineTiles = 1, kEngineMfmaWg = 2 };
 
 }  // namespace bv

@@ -51,10 +51,49 @@ struct AdjArgs {
 };
 
 hipError_t launch_adjoint(int cfg, bool fp32, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+size_t adjoint_lds_need(int cfg, bool fp32, int ldx);   // LDS bytes of one launch
 hipError_t launch_coefficients(int cfg, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+// matrix-core engine: g tile rows (1..11); mode 0 value, 1 value + gradient, 2 coefficients (FP64)
+hipError_t launch_mfma(int g, bool fp32, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+size_t mfma_lds_need(int g, bool fp32, int mode, int ldx);   // dynamic LDS bytes of one launch
+// one-wave matrix-core kernels (mode 0 value, 1 value + gradient); FP32 up to
+// G = kWaveMaxG32 tile rows, FP64 up to kWaveMaxG64 (above G = 8 the FP64 tiles
+// exceed the register file and part of them spills to scratch)
+constexpr int kWaveMaxG32 = 11;
+constexpr int kWaveMaxG64 = 11;
+constexpr int kWaveChunk = 32;  // adjoint right-hand sides per pass (bounds the LDS of any block)
+bool wave_fits(int g, bool fp32);
+hipError_t launch_wave_f32(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+hipError_t launch_wave_f64(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+hipError_t launch_wave(int g, bool fp32, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+struct LargeArgs {
+  const double* locs;
+  const double* y;
+  const int* block_ptr;
+  const int* nbr_ptr;
+  const int* nbr_idx;
+  const int* sched;
+  const int* list;
+  const int* list_count;
+  int nsched;
+  int ntheta;
+  int bc;
+  int d;
+  int fp32_guard;
+  int flag_or;
+  void* ws;              // nslots x slot_elems elements
+  int64_t slot_elems;    // P_max^2
+  double* partial;
+  int* flag;
+};
+constexpr int kLargeCfg = 31;   // size class of blocks above the register capacity
+hipError_t launch_large(bool fp32, const LargeArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+
+// leading dimension of the LDS right-hand sides for l_max (matrix-core engine)
+inline int mfma_ldx(int nr_max) { return 16 * ((nr_max + 15) / 16) + 1; }
 
 hipError_t launch_classify(const int* block_ptr, const int* nbr_ptr, int bc, int* cfg_of, int* counts,
-                           unsigned long long* stats, int* maxes, hipStream_t s);
+                           unsigned long long* stats, int* maxes, int* lmax_cfg, int engine, hipStream_t s);
 hipError_t launch_scatter(const int* cfg_of, int bc, const int* cfg_off, int* cursor, int* sched, hipStream_t s);
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 hipError_t launch_compact_flagged(const int* sched, int nsched, int ntheta, int bc, const int* flag, int* list,

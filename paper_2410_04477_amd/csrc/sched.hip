@@ -9,16 +9,20 @@ namespace bv {
 // workload statistics (exact integer sums, so they are deterministic).
 __global__ void classify_kernel(const int* __restrict__ block_ptr, const int* __restrict__ nbr_ptr, int bc,
                                 int* __restrict__ cfg_of, int* __restrict__ counts, unsigned long long* __restrict__ stats,
-                                int* __restrict__ maxes) {
+                                int* __restrict__ maxes, int* __restrict__ lmax_cfg, int engine) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= bc) return;
   const int l = block_ptr[b + 1] - block_ptr[b];
   const int m = nbr_ptr[b + 1] - nbr_ptr[b];
   const int p = l + m;
-  int c = cfg_for_joint(p);
+  int c = engine == kEngineTiles ? cfg_for_joint(p) : cfg_mfma_for_joint(p);
+  if (c < 0 && p <= 16383) c = kLargeCfg;   // served by the global-workspace kernel
   if (l <= 0 || m < 0) c = -2;
   cfg_of[b] = c;
-  if (c >= 0) atomicAdd(&counts[c], 1);
+  if (c >= 0) {
+    atomicAdd(&counts[c], 1);
+    atomicMax(&lmax_cfg[c], l);
+  }
   const unsigned long long pp = (unsigned long long)p;
   atomicAdd(&stats[0], pp * pp * pp);
   atomicAdd(&stats[1], pp * pp);
@@ -125,9 +129,9 @@ namespace bv {
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 hipError_t launch_classify(const int* block_ptr, const int* nbr_ptr, int bc, int* cfg_of, int* counts,
-                           unsigned long long* stats, int* maxes, hipStream_t s) {
+                           unsigned long long* stats, int* maxes, int* lmax_cfg, int engine, hipStream_t s) {
   hipLaunchKernelGGL(classify_kernel, dim3(cdiv(bc, 256)), dim3(256), 0, s, block_ptr, nbr_ptr, bc, cfg_of, counts,
-                     stats, maxes);
+                     stats, maxes, lmax_cfg, engine);
   return hipGetLastError();
 }
 

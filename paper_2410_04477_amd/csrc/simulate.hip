@@ -59,7 +59,7 @@ SimLayout sim_layout(int64_t n, int64_t nnz, int64_t nt) {
   L.cfg = o;    o = al256s(o + sizeof(int) * n);
   L.sched = o;  o = al256s(o + sizeof(int) * n);
   L.counts = o; o = al256s(o + sizeof(int) * 64);
-  L.stats = o;  o = al256s(o + sizeof(unsigned long long) * 8 + sizeof(int) * 16);
+  L.stats = o;  o = al256s(o + sizeof(unsigned long long) * 8 + sizeof(int) * (16 + 32));
   L.coef = o;   o = al256s(o + sizeof(double) * (nnz > 0 ? nnz : 1) * nt);
   L.cvar = o;   o = al256s(o + sizeof(double) * n * nt);
   L.flag = o;   o = al256s(o + sizeof(int) * n * nt);
@@ -118,19 +118,20 @@ extern "C" int vecchia_simulate(const double* locs_ord, int64_t n, int32_t d, co
   const int ni = (int)n;
   hipLaunchKernelGGL(unit_blocks_kernel, dim3((ni + 256) / 256), dim3(256), 0, s, bp, ni);
   SCHECK(launch_fill_int(counts, 64, 0, s));
-  SCHECK(launch_fill_int(reinterpret_cast<int*>(stats), 16 + 16, 0, s));
-  SCHECK(launch_classify(bp, nbr_ptr, ni, cfg, counts, stats, maxes, s));
+  int* lmax_cfg = maxes + 16;
+  SCHECK(launch_fill_int(reinterpret_cast<int*>(stats), 16 + 16 + 32, 0, s));
+  SCHECK(launch_classify(bp, nbr_ptr, ni, cfg, counts, stats, maxes, lmax_cfg, kEngineMfmaWg, s));
   int hc[32], hmax[4];
   SCHECK(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, s));
   SCHECK(hipMemcpyAsync(hmax, maxes, sizeof(hmax), hipMemcpyDeviceToHost, s));
   SCHECK(hipStreamSynchronize(s));
   if (hmax[3] > 0) return hmax[0] > VECCHIA_MAX_JOINT ? VECCHIA_EUNSUPPORTED : VECCHIA_EINVAL;
   int hoff[32], acc = 0;
-  for (int c = 0; c < kNumCfgs; ++c) {
+  for (int c = 0; c < kMfmaMaxG; ++c) {
     hoff[c] = acc;
     acc += hc[c];
   }
-  SCHECK(hipMemcpyAsync(counts + 32, hoff, sizeof(int) * kNumCfgs, hipMemcpyHostToDevice, s));
+  SCHECK(hipMemcpyAsync(counts + 32, hoff, sizeof(int) * kMfmaMaxG, hipMemcpyHostToDevice, s));
   SCHECK(launch_fill_int(counts, 32, 0, s));
   SCHECK(launch_scatter(cfg, ni, counts + 32, counts, sched, s));
   AdjArgs a;
@@ -144,15 +145,15 @@ extern "C" int vecchia_simulate(const double* locs_ord, int64_t n, int32_t d, co
   a.bc = ni;
   a.coef_stride = hnnz;
   a.d = d;
-  a.ldx = 1;
+  a.ldx = mfma_ldx(1);
   a.flag = at<int>(workspace, L.flag);
   a.coef = at<double>(workspace, L.coef);
   a.cvar = at<double>(workspace, L.cvar);
-  for (int c = 0; c < kNumCfgs; ++c) {
+  for (int c = 0; c < kMfmaMaxG; ++c) {
     if (hc[c] == 0) continue;
     a.sched = sched + hoff[c];
     a.nsched = hc[c];
-    SCHECK(launch_coefficients(c, a, thp, hc[c] * ntheta, s));
+    SCHECK(launch_mfma(c + 1, false, 2, a, thp, hc[c] * ntheta, s));
   }
   // recursion in passes
   int* done = at<int>(workspace, L.done);

@@ -24,10 +24,18 @@ class MLEResult:
 
 
 def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 200, tol_rel: float = 1e-10,
-        history: int = 10) -> MLEResult:
+        history: int = 10, polish_evals: int = 30) -> MLEResult:
     """L-BFGS (strong Wolfe line search) on eta = log(sigma2, range, nugget + floor),
     minimising -l / n.  Stops on relative change < tol_rel, small gradient, or
-    max_evals evaluations."""
+    max_evals evaluations.  With an FP32-bulk precision, a short FP64 L-BFGS
+    pass (at most polish_evals evaluations) starts from the FP32 optimum: the
+    FP32 gradient's rounding error can stop the line search early near the
+    optimum, where the exact gradient is small."""
+    if precision != "fp64" and polish_evals > 0:
+        first = fit(model, theta0, precision, max_evals, tol_rel, history, 0)
+        second = fit(model, first.theta, "fp64", polish_evals, tol_rel, history, 0)
+        return MLEResult(second.theta, second.loglik, first.evals + second.evals, first.iters + second.iters,
+                         first.seconds + second.seconds, second.converged)
     s2, rg, nug = (float(v) for v in theta0)
     eta = torch.tensor([math.log(s2), math.log(rg), math.log(nug + NUGGET_FLOOR)], dtype=torch.float64,
                        requires_grad=True)

@@ -22,7 +22,7 @@ class BlockVecchia:
 
     def __init__(self, locs, y, bc: int, m: int, nu: float, init_idx, block_perm,
                  aniso: Sequence[float] = (1.0, 1.0, 1.0), kmeans_iters: int = 30, max_theta: int = 1,
-                 device: str = "cuda"):
+                 device: str = "cuda", engine: str = "mfma"):
         dev = torch.device(device)
         def t(a, dt):
             a = a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a))
@@ -40,11 +40,11 @@ class BlockVecchia:
         self.nbr_ptr, self.nbr_idx = api.neighbors(self.locs_perm, self.block_ptr, m, self.metric)
         if self.nbr_idx.numel() == 0:
             self.nbr_idx = torch.zeros(1, dtype=torch.int32, device=dev)
-        self.plan = api.Plan(self.block_ptr, self.nbr_ptr, self.n, max_theta)
+        self.plan = api.Plan(self.block_ptr, self.nbr_ptr, self.n, max_theta, engine)
 
     @classmethod
     def from_prepared(cls, locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, nu, aniso=(1.0, 1.0, 1.0),
-                      max_theta: int = 1):
+                      max_theta: int = 1, engine: str = "mfma"):
         """Wrap device tensors that are already in block order."""
         self = cls.__new__(cls)
         self.locs_perm, self.y_perm = locs_perm, y_perm
@@ -55,7 +55,7 @@ class BlockVecchia:
         self.aniso = tuple(float(a) for a in aniso) + (1.0,) * (3 - len(aniso))
         self.metric = [1.0 / a for a in self.aniso[: self.d]]
         self.perm = None
-        self.plan = api.Plan(block_ptr, nbr_ptr, self.n, max_theta)
+        self.plan = api.Plan(block_ptr, nbr_ptr, self.n, max_theta, engine)
         return self
 
     def theta(self, sigma2: float, range_: float, nugget: float):

@@ -4,26 +4,30 @@ Gradient tolerances (norm-wise, ||dg|| / ||g||): FP64 adjoint vs the oracle's
 trace-formula gradient <= 1e-8; vs central finite differences of the FP64
 log-likelihood (h = 1e-5 absolute on the natural parameters) within their
 own step-halving truncation estimate, and vs the Richardson-extrapolated
-difference <= 1e-6; FP32-bulk gradient vs FP64 <= 1e-3."""
+difference <= 1e-6; FP32-bulk gradient vs FP64 <= 1e-3 (norm-wise on per-block
+terms, or per component on the cancellation-free scale sum_i |dl_i| for
+totals near the truth)."""
 import numpy as np
 import pytest
 import torch
 
 import workloads as W
-from cases import problem, workload_problem
+from cases import oracle_terms, problem, workload_problem
 from oracle import coracle
 
 pytestmark = pytest.mark.gpu
+# one-wave matrix-core (default), four-wave matrix-core, vector-ALU register tiles
+ENGINES = ["mfma", "mfma_wg", "tiles"]
 DEV = "cuda"
 
 
-def _model(pb, nu, aniso=(1.0, 1.0, 1.0), max_theta=1):
+def _model(pb, nu, aniso=(1.0, 1.0, 1.0), max_theta=1, engine="mfma"):
     from paper_2410_04477_amd.model import BlockVecchia
     t = lambda a, dt: torch.tensor(np.asarray(a), dtype=dt, device=DEV)
     nidx = pb["nbr_idx"] if len(pb["nbr_idx"]) else np.zeros(1)
     return BlockVecchia.from_prepared(t(pb["locs_perm"], torch.float64), t(pb["y_perm"], torch.float64),
                                       t(pb["block_ptr"], torch.int32), t(pb["nbr_ptr"], torch.int32),
-                                      t(nidx, torch.int32), nu, aniso, max_theta)
+                                      t(nidx, torch.int32), nu, aniso, max_theta, engine)
 
 
 def _oracle_grad(pb, th):
@@ -36,11 +40,12 @@ def _rel(a, b):
 
 @pytest.mark.parametrize("m,bc,nu,d", [(0, 60, 1.5, 2), (12, 60, 0.5, 2), (30, 100, 1.5, 2), (60, 100, 2.5, 3),
                                        (100, 120, 1.5, 2), (140, 300, 2.5, 3), (160, 600, 0.5, 2)])
-def test_adjoint_matches_oracle_per_block(m, bc, nu, d):
+@pytest.mark.parametrize("engine", ENGINES)
+def test_adjoint_matches_oracle_per_block(m, bc, nu, d, engine):
     aniso = (1.0, 1.0, 0.3) if d == 3 else (1.0, 1.0, 1.0)
     th = W.Theta(1.2, 0.06, 2e-3, nu, aniso)
     pb = problem(f"g{m}", 1500, d, bc, m, th, 50 + m, zmax=0.3)
-    mod = _model(pb, nu, aniso)
+    mod = _model(pb, nu, aniso, engine=engine)
     ll, g, cnt, part, gpart = mod.loglik_grad([mod.theta(th.sigma2, th.beta, th.nugget)], "fp64", True)
     ref = _oracle_grad(pb, th)
     gp = gpart[0].cpu().numpy()
@@ -49,6 +54,31 @@ def test_adjoint_matches_oracle_per_block(m, bc, nu, d):
     # the value path of the adjoint kernel equals the forward kernel's
     llf = mod.loglik([mod.theta(th.sigma2, th.beta, th.nugget)])[0]
     assert abs(float(ll[0]) - float(llf[0])) <= 1e-12 * abs(float(llf[0]))
+
+
+@pytest.mark.parametrize("engine", ENGINES)
+@pytest.mark.parametrize("bc,m", [(18, 20), (40, 0)])
+def test_adjoint_many_right_hand_sides(bc, m, engine):
+    """Blocks of about 40-85 points, so l_i + 2 right-hand sides exceed one
+    32-column pass of the one-wave adjoint (several passes, the factor kept in
+    the tiles).  Engines that hold the right-hand sides whole in LDS either fit
+    or report VECCHIA_EUNSUPPORTED, never a wrong value."""
+    from paper_2410_04477_amd._lib import VecchiaError
+    th = W.Theta(1.1, 0.08, 1e-3, 1.5)
+    pb = problem(f"rhs{bc}", 1500, 2, bc, m, th, 71 + bc)
+    assert np.diff(pb["block_ptr"]).max() + 2 > 32   # at least two passes of 32
+    mod = _model(pb, 1.5, engine=engine)
+    t = [mod.theta(th.sigma2, th.beta, th.nugget)]
+    try:
+        ll, g, cnt, part, gpart = mod.loglik_grad(t, "fp64", True)
+    except VecchiaError as e:
+        assert engine != "mfma" and "unsupported" in str(e), str(e)
+        return
+    ref = _oracle_grad(pb, th)
+    np.testing.assert_allclose(gpart[0].cpu().numpy(), ref, rtol=1e-7, atol=1e-8 * np.abs(ref).max())
+    np.testing.assert_allclose(part[0].cpu().numpy(), oracle_terms(pb, th), rtol=1e-9, atol=1e-9)
+    _, _, _, _, gpart32 = mod.loglik_grad(t, "fp32", True)
+    assert _rel(gpart32[0].cpu().numpy(), ref) <= 1e-3
 
 
 def test_adjoint_vs_central_fd_and_fp32():
@@ -84,10 +114,11 @@ def test_adjoint_vs_central_fd_and_fp32():
     assert _rel(g32[0].cpu().numpy(), g) <= 1e-3
 
 
-def test_fp32_forced_refactor_gradient_equals_fp64():
+@pytest.mark.parametrize("engine", ENGINES)
+def test_fp32_forced_refactor_gradient_equals_fp64(engine):
     th = W.Theta(1.0, 0.05, 1e-3, 2.5)
     pb = problem("gforce", 2000, 2, 200, 40, th, 62, ysim="block")
-    mod = _model(pb, 2.5)
+    mod = _model(pb, 2.5, engine=engine)
     t = [mod.theta(th.sigma2, th.beta, th.nugget)]
     l64, g64, _, _, _ = mod.loglik_grad(t, "fp64")
     lf, gf, cnt, _, _ = mod.loglik_grad(t, "fp32_force_refactor")
@@ -104,9 +135,14 @@ def test_c4_full_size_gradient_vs_oracle():
     ll, g, cnt, _, _ = mod.loglik_grad([mod.theta(t.sigma2, t.beta, t.nugget) for t in thetas], "fp64")
     ll32, g32, _, _, _ = mod.loglik_grad([mod.theta(t.sigma2, t.beta, t.nugget) for t in thetas], "fp32")
     for i, th in enumerate(thetas):
-        ref = _oracle_grad(pb, th).sum(0)
+        terms = _oracle_grad(pb, th)
+        ref = terms.sum(0)
         assert _rel(g[i].cpu().numpy(), ref) <= 1e-8
-        assert _rel(g32[i].cpu().numpy(), ref) <= 1e-3
+        # FP32: each block's terms carry a relative error of order kappa * u32; near
+        # the truth the block terms cancel in the sum, so the bound is taken on the
+        # cancellation-free scale sum_i |dl_i|, per component
+        scale = np.abs(terms).sum(0)
+        assert np.all(np.abs(g32[i].cpu().numpy() - ref) <= 1e-3 * scale), (g32[i], ref, scale)
         ref_ll = coracle.loglik(pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"], th)
         assert abs(float(ll[i]) - ref_ll) <= 1e-8 * abs(ref_ll)
         assert abs(float(ll32[i]) - ref_ll) <= 1e-4 * abs(ref_ll)
