@@ -27,8 +27,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "block-Vecchia loglik evals/s and points/s at n=1e6, FP32 vs FP64 @1e-4 rel err"
-FP32_VECTOR_PEAK = 157.3e12   # MI355X published FP32 vector FLOP/s
-FP64_VECTOR_PEAK = 78.6e12
+FP32_PEAK = 157.3e12   # MI355X published FP32 peak (vector and dense matrix) FLOP/s
+FP64_PEAK = 78.6e12
 
 
 def log(msg: str) -> None:
@@ -37,7 +37,8 @@ def log(msg: str) -> None:
 
 def kernel_source_sha() -> str:
     h = hashlib.sha256()
-    for f in ("bv_mfma.hip", "bv_adjoint.hip", "bv_forward.hip", "common.hpp"):
+    for f in ("wave_kernel.hpp", "bv_wave_f32.hip", "bv_wave_f64.hip", "bv_mfma.hip", "bv_adjoint.hip",
+              "bv_forward.hip", "common.hpp", "internal.hpp", "api.hip"):
         with open(os.path.join(ROOT, "paper_2410_04477_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -56,13 +57,17 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C3")
-    ap.add_argument("--engine", default="mfma", choices=["mfma", "tiles"])
+    ap.add_argument("--engine", default="mfma", choices=["mfma", "mfma_wg", "tiles"])
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration under rocprofv3)")
+    ap.add_argument("--print-sha", action="store_true", help="print the kernel source hash and exit")
     args = ap.parse_args()
+    if args.print_sha:
+        print(kernel_source_sha())
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1).", file=sys.stderr)
         return 2
@@ -158,7 +163,8 @@ def main() -> int:
     avg_launch_s = ms_dom / n_dom / 1e3
     achieved = flops_launch / avg_launch_s
     R, G = api.tile_config(cfg_dom, plan.engine)
-    kname = (f"bv_mfma_kernel<float,{G},1>" if plan.engine == "mfma" else f"bv_adj_kernel<float,{R},{G},0>")
+    kname = {"mfma": f"bv_wave_kernel<float,{G},1>", "mfma_wg": f"bv_mfma_kernel<float,{G},1>"}.get(
+        plan.engine, f"bv_adj_kernel<float,{R},{G},0>")
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if os.path.exists(tpath):
@@ -167,8 +173,8 @@ def main() -> int:
         ent = tr.get(kname)
         if ent and tr.get("kernel_source_sha") == kernel_source_sha():
             traffic = ent.get("bytes_per_launch")
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": FP32_VECTOR_PEAK / 1e12, "unit": "TFLOP/s",
-                "frac": achieved / FP32_VECTOR_PEAK, "traffic": traffic,
+    roofline = {"bound": "alu" if plan.engine == "tiles" else "mfma", "achieved": achieved / 1e12,
+                "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
                 "kernel": kname, "blocks_per_launch": int(blk.size),
                 "avg_launch_ms": avg_launch_s * 1e3, "flops_per_launch": flops_launch,
                 "share_of_step": ms_dom / (1e3 * gpu_s) if gpu_s > 0 else None}

@@ -152,10 +152,13 @@ typedef enum { VECCHIA_ENGINE_MFMA = 0, VECCHIA_ENGINE_TILES = 1, VECCHIA_ENGINE
  *   workspace    >= vecchia_plan_workspace_size(bc, max_theta) bytes
  * Blocks with m_i + l_i above VECCHIA_MAX_JOINT (up to 16383) form a size class
  * of their own: each is generated into a global workspace and factored
- * left-looking in 16-column panels with MFMA panel updates.  They need a
- * second workspace of plan->large_ws_bytes, attached with
- * vecchia_plan_attach_large before the first evaluation; vecchia_loglik_grad
- * returns VECCHIA_EUNSUPPORTED for them. */
+ * left-looking in 16-column panels with MFMA panel updates;
+ * vecchia_loglik_grad returns VECCHIA_EUNSUPPORTED for them.
+ * Auxiliary workspace: plan->aux_ws_bytes bytes (0 when not needed), attached
+ * with vecchia_plan_attach_aux before the first evaluation, holds the large
+ * blocks' matrices and, for engine MFMA, the adjoint's per-block factor tiles
+ * (at most 4 GiB; the adjoint launches in chunks that fit it).  One plan's
+ * calls must not overlap in time (they share both workspaces). */
 #define VECCHIA_MAX_BUCKETS 24
 #define VECCHIA_MAX_JOINT 175  /* largest m_i + l_i (both engines) */
 typedef struct {
@@ -174,10 +177,10 @@ typedef struct {
   void* timing;   /* NULL unless vecchia_plan_set_timing enabled per-launch timing */
   int32_t engine; /* vecchia_engine of the kernels this plan schedules */
   int64_t nlarge;            /* blocks with m_i + l_i > VECCHIA_MAX_JOINT */
-  size_t large_ws_bytes;     /* workspace they need (vecchia_plan_attach_large) */
-  int32_t large_slots;       /* blocks factored concurrently */
-  int64_t large_slot_elems;  /* elements per slot */
-  void* large_ws;
+  int32_t large_slots;       /* large blocks factored concurrently */
+  int64_t large_slot_elems;  /* elements per large-block slot */
+  size_t aux_ws_bytes;       /* auxiliary workspace needed (vecchia_plan_attach_aux) */
+  void* aux_ws;
   int32_t bucket_lmax[VECCHIA_MAX_BUCKETS];  /* largest l_i of each class */
   int32_t lds_bytes;                          /* device LDS limit per workgroup */
 } vecchia_plan;
@@ -191,7 +194,7 @@ int vecchia_tile_config(int32_t engine, int32_t cfg, int32_t* R, int32_t* G);
 int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, const int32_t* nbr_ptr,
                       int64_t n, int64_t bc, int32_t max_theta, int32_t engine,
                       void* workspace, size_t ws_bytes, void* stream);
-int vecchia_plan_attach_large(vecchia_plan* plan, void* large_workspace, size_t bytes);
+int vecchia_plan_attach_aux(vecchia_plan* plan, void* aux_workspace, size_t bytes);
 
 /* Per-launch timing for benchmarks.  When enabled, vecchia_loglik and
  * vecchia_loglik_grad bracket every size-class kernel launch with hipEvents

@@ -32,8 +32,8 @@ class Plan(ctypes.Structure):
                 ("off_sched", ctypes.c_size_t), ("off_partial", ctypes.c_size_t), ("off_flag", ctypes.c_size_t),
                 ("off_list", ctypes.c_size_t), ("off_count", ctypes.c_size_t), ("off_chunk", ctypes.c_size_t),
                 ("off_grad", ctypes.c_size_t), ("timing", ctypes.c_void_p), ("engine", ctypes.c_int32),
-                ("nlarge", ctypes.c_int64), ("large_ws_bytes", ctypes.c_size_t), ("large_slots", ctypes.c_int32),
-                ("large_slot_elems", ctypes.c_int64), ("large_ws", ctypes.c_void_p),
+                ("nlarge", ctypes.c_int64), ("large_slots", ctypes.c_int32), ("large_slot_elems", ctypes.c_int64),
+                ("aux_ws_bytes", ctypes.c_size_t), ("aux_ws", ctypes.c_void_p),
                 ("bucket_lmax", ctypes.c_int32 * MAX_BUCKETS), ("lds_bytes", ctypes.c_int32)]
 
 
@@ -66,7 +66,7 @@ SIGNATURES = {
     "vecchia_colsum": (ctypes.c_int, [P, I32, I32, I32, P, P]),
     "vecchia_adam": (ctypes.c_int, [P, P, P, P, I64, D, D, D, D, I64, P]),
     "vecchia_tile_config": (ctypes.c_int, [I32, I32, P, P]),
-    "vecchia_plan_attach_large": (ctypes.c_int, [P, P, SZ]),
+    "vecchia_plan_attach_aux": (ctypes.c_int, [P, P, SZ]),
     "vecchia_plan_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
     "vecchia_plan_timing": (ctypes.c_int, [P, P, P, ctypes.c_int]),
 }

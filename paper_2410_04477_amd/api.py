@@ -125,11 +125,11 @@ class Plan:
                                       ENGINES[engine], _p(self.ws), self.ws.numel(), _stream(block_ptr.device)),
                 "vecchia_plan_init")
         self.engine = engine
-        self.large_ws = None
-        if self.c.nlarge > 0:
-            self.large_ws = torch.empty(int(self.c.large_ws_bytes), dtype=torch.uint8, device=block_ptr.device)
-            L.check(lib.vecchia_plan_attach_large(ctypes.byref(self.c), _p(self.large_ws), self.large_ws.numel()),
-                    "vecchia_plan_attach_large")
+        self.aux_ws = None
+        if self.c.aux_ws_bytes > 0:
+            self.aux_ws = torch.empty(int(self.c.aux_ws_bytes), dtype=torch.uint8, device=block_ptr.device)
+            L.check(lib.vecchia_plan_attach_aux(ctypes.byref(self.c), _p(self.aux_ws), self.aux_ws.numel()),
+                    "vecchia_plan_attach_aux")
         self.block_ptr, self.nbr_ptr = block_ptr, nbr_ptr
 
     @property

@@ -6,7 +6,9 @@ from __future__ import annotations
 
 import concurrent.futures as cf
 import glob
+import json
 import os
+import re
 import subprocess
 import sys
 
@@ -16,6 +18,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libvecchia.so")
+RESOURCES = os.path.join(BUILD, "kernel_resources.json")   # per-kernel registers / scratch / occupancy
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -24,13 +27,19 @@ CFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-command-line-argument"]
 
 
-def _compile(src: str) -> str:
+_REMARK = re.compile(r"Function Name: (\S+).*?VGPRs: (\d+).*?AGPRs: (\d+).*?ScratchSize \[bytes/lane\]: (\d+)"
+                     r".*?Occupancy \[waves/SIMD\]: (\d+).*?LDS Size \[bytes/block\]: (\d+)", re.S)
+
+
+def _compile(src: str):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC, *CFLAGS, "-c", src, "-o", obj]
+    cmd = [HIPCC, *CFLAGS, "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
-    return obj
+    res = {m[0]: {"vgpr": int(m[1]), "agpr": int(m[2]), "scratch": int(m[3]), "occupancy": int(m[4]),
+                  "lds_static": int(m[5])} for m in _REMARK.findall(r.stderr)}
+    return obj, res
 
 
 def build(jobs: int | None = None, verbose: bool = False) -> str:
@@ -39,7 +48,13 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
     jobs = jobs or min(8, len(srcs), os.cpu_count() or 4)
     with cf.ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        outs = list(ex.map(_compile, srcs))
+    objs = [o for o, _ in outs]
+    resources = {}
+    for _, res in outs:
+        resources.update(res)
+    with open(RESOURCES, "w") as fh:
+        json.dump(resources, fh, indent=0, sort_keys=True)
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)

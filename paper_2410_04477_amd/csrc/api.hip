@@ -157,7 +157,18 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
     const int64_t work = plan->nlarge * (int64_t)max_theta;
     plan->large_slots = (int32_t)(work < 256 ? work : 256);
     plan->large_slot_elems = P * P;
-    plan->large_ws_bytes = (size_t)plan->large_slots * (size_t)(P * P) * sizeof(double);
+    plan->aux_ws_bytes = (size_t)plan->large_slots * (size_t)(P * P) * sizeof(double);
+  }
+  if (engine == kEngineMfma) {
+    // adjoint factor tiles: every work item of the largest class, FP64, capped
+    size_t need = 0;
+    for (int c = 0; c < kMfmaMaxG; ++c)
+      if (hcounts[c] > 0 && wave_fits(c + 1, false)) {
+        const size_t b = (size_t)hcounts[c] * (size_t)max_theta * wave_tile_bytes(c + 1, false);
+        need = b > need ? b : need;
+      }
+    if (need > kAdjTileCap) need = kAdjTileCap;
+    if (need > plan->aux_ws_bytes) plan->aux_ws_bytes = need;
   }
   plan->bucket_off[nb] = acc;
   plan->nbuckets = nb;
@@ -223,7 +234,20 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
                              int grid, hipStream_t s) {
   const int g = plan->bucket_cfg[q] + 1;
   if (plan->engine == kEngineMfma && wave_fits(g, fp32)) {
-    VCHECK_HIP(launch_wave(g, fp32, mode, a, thp, grid, s));
+    if (mode == 0) {
+      VCHECK_HIP(launch_wave(g, fp32, 0, a, thp, grid, s));
+      return VECCHIA_OK;
+    }
+    // adjoint: as many work items per launch as the tile buffer holds
+    const size_t per = wave_tile_bytes(g, fp32);
+    const size_t cap = plan->aux_ws_bytes / per;
+    if (cap == 0) return VECCHIA_ENOMEM;
+    const int chunk = cap < (size_t)grid ? (int)cap : grid;
+    a.tiles = plan->aux_ws;
+    for (int w0 = 0; w0 < grid; w0 += chunk) {
+      a.item_base = w0;
+      VCHECK_HIP(launch_wave(g, fp32, 1, a, thp, grid - w0 < chunk ? grid - w0 : chunk, s));
+    }
     return VECCHIA_OK;
   }
   a.ldx = mfma_ldx(plan->bucket_lmax[q] + 2);
@@ -311,12 +335,12 @@ extern "C" int vecchia_plan_timing(vecchia_plan* plan, double* ms, int64_t* laun
   return VECCHIA_OK;
 }
 
-extern "C" int vecchia_plan_attach_large(vecchia_plan* plan, void* large_workspace, size_t bytes) {
+extern "C" int vecchia_plan_attach_aux(vecchia_plan* plan, void* aux_workspace, size_t bytes) {
   if (!plan) return VECCHIA_EINVAL;
-  if (plan->nlarge == 0) return VECCHIA_OK;
-  if (!large_workspace) return VECCHIA_EINVAL;
-  if (bytes < plan->large_ws_bytes) return VECCHIA_ENOMEM;
-  plan->large_ws = large_workspace;
+  if (plan->aux_ws_bytes == 0) return VECCHIA_OK;
+  if (!aux_workspace) return VECCHIA_EINVAL;
+  if (bytes < plan->aux_ws_bytes) return VECCHIA_ENOMEM;
+  plan->aux_ws = aux_workspace;
   return VECCHIA_OK;
 }
 
@@ -337,7 +361,7 @@ static LargeArgs as_large(const FwdArgs& f, const vecchia_plan* plan) {
   a.d = f.d;
   a.fp32_guard = f.fp32_guard;
   a.flag_or = f.flag_or;
-  a.ws = plan->large_ws;
+  a.ws = plan->aux_ws;
   a.slot_elems = plan->large_slot_elems;
   a.partial = f.partial;
   a.flag = f.flag;
@@ -369,7 +393,7 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
   int st = check_common(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision);
   if (st) return st;
   if (!loglik) return VECCHIA_EINVAL;
-  if (plan->nlarge > 0 && !plan->large_ws) return VECCHIA_ENOMEM;
+  if (plan->aux_ws_bytes > 0 && !plan->aux_ws) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const int bc = (int)plan->bc;
   void* ws = plan->ws;
@@ -459,6 +483,7 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
   if (st) return st;
   if (!loglik || !grad) return VECCHIA_EINVAL;
   if (plan->nlarge > 0) return VECCHIA_EUNSUPPORTED;  // gradient above the register capacity
+  if (plan->aux_ws_bytes > 0 && !plan->aux_ws) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const int bc = (int)plan->bc;
   void* ws = plan->ws;

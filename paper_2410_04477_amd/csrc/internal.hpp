@@ -48,6 +48,8 @@ struct AdjArgs {
   double* coef;          // coefficient mode: conditional-mean weights, CSR like nbr_idx, one copy per theta
   double* cvar;          // coefficient mode: conditional variance per block and theta
   int64_t coef_stride;   // coefficient mode: entries per theta (nbr_ptr[bc])
+  void* tiles;           // one-wave adjoint: factor tiles, one slot per work item of the launch
+  int item_base;         // first work item of the launch (launches in chunks of the tile buffer)
 };
 
 hipError_t launch_adjoint(int cfg, bool fp32, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
@@ -62,6 +64,9 @@ size_t mfma_lds_need(int g, bool fp32, int mode, int ldx);   // dynamic LDS byte
 constexpr int kWaveMaxG32 = 11;
 constexpr int kWaveMaxG64 = 11;
 constexpr int kWaveChunk = 32;  // adjoint right-hand sides per pass (bounds the LDS of any block)
+// bytes of one work item's factor tiles in the adjoint's tile buffer, and the buffer's cap
+inline size_t wave_tile_bytes(int g, bool fp32) { return (size_t)g * (g + 1) / 2 * 256 * (fp32 ? 4 : 8); }
+constexpr size_t kAdjTileCap = (size_t)4 << 30;
 bool wave_fits(int g, bool fp32);
 hipError_t launch_wave_f32(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 hipError_t launch_wave_f64(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);

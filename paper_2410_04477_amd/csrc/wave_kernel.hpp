@@ -83,8 +83,13 @@ __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
   return 6 * 16 * G + (mode == 0 ? 4 * 16 * G : 16 * G * (kWaveChunk + 1) + 16 * 16 * G + 16);
 }
 
+// Two waves per SIMD where the register file holds them without spilling
+// (FP32 up to G = 9); one otherwise.
+template <typename T, int G>
+constexpr int wave_min_waves() { return sizeof(T) == 4 && G <= 9 ? 2 : 1; }
+
 template <typename T, int G, int MODE>
-__global__ void __launch_bounds__(64) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
+__global__ void __launch_bounds__(64, (wave_min_waves<T, G>())) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
   constexpr int P = 16 * G;
   constexpr int NT = G * (G + 1) / 2;
   typedef WMma<T> M;
@@ -98,7 +103,7 @@ __global__ void __launch_bounds__(64) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
 
   const int ln = threadIdx.x, lr = ln & 15, lg = ln >> 4;
   const int total = a.list ? *a.list_count : a.nsched * a.ntheta;
-  const int wi = blockIdx.x;
+  const int wi = blockIdx.x + a.item_base;
   if (wi >= total) return;
   int b, tt;
   if (a.list) {
@@ -212,26 +217,20 @@ __global__ void __launch_bounds__(64) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
       for (int q = 0; q < (P - K * 16 + 63) / 64; ++q) {
         const int i = K * 16 + ln + 64 * q;
         if (i < P) {
+          // branch-free: every lane runs the substitution, then rows above the
+          // block take zero and rows inside it take L_dd
+          const int di = i - k0;
           T x[4];
-          if (i < k0) {
 #pragma unroll
-            for (int c = 0; c < 4; ++c) x[c] = T(0);
-          } else if (i < k0 + 4) {
+          for (int c = 0; c < 4; ++c) {
+            T v = pan[c * P + i];
 #pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              T v = T(0);
+            for (int j = 0; j < c; ++j) v -= x[j] * Ld[c][j];
+            const T t = (k0 + c < p) ? v * rinv[c] : T(0);
+            T v2 = t;
 #pragma unroll
-              for (int rr = 0; rr < 4; ++rr) v = (i - k0 == rr) ? Ld[rr][c] : v;
-              x[c] = v;
-            }
-          } else {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) {
-              T v = pan[c * P + i];
-#pragma unroll
-              for (int j = 0; j < c; ++j) v -= x[j] * Ld[c][j];
-              x[c] = (k0 + c < p) ? v * rinv[c] : T(0);
-            }
+            for (int rr = 0; rr < 4; ++rr) v2 = di == rr ? Ld[rr][c] : v2;
+            x[c] = di < 0 ? T(0) : v2;
           }
 #pragma unroll
           for (int c = 0; c < 4; ++c) pan[c * P + i] = x[c];
@@ -300,6 +299,16 @@ __global__ void __launch_bounds__(64) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
     }
     return;
   }
+  // the factor leaves the registers for this item's slot of the tile buffer
+  // (accumulator order, 256 elements per tile); the adjoint reads it back one
+  // tile row at a time, so its phases do not hold the tiles in registers
+  T* Lg = reinterpret_cast<T*>(a.tiles) + (size_t)(wi - a.item_base) * (NT * 256);
+  static_for<0, NT>(BV_CI(t) {
+    BV_CV(t);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Lg[t * 256 + ln * 4 + r] = acc[t][r];
+  });
+  __syncthreads();
 
   // ---- adjoint: X <- L^-T X and the contraction, kWaveChunk right-hand sides at a time
   // (the factor stays in the tiles, so a chunk only repeats the triangular solves)
@@ -322,35 +331,23 @@ __global__ void __launch_bounds__(64) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
     for (int c = ln; c < nc; c += 64)
       if (cb + c >= 2) X[(m + cb + c - 2) * LDX + c] = T(1);
     if (cb == 0) {
-      static_for<0, G>(BV_CI(I) {
-        BV_CV(I);
-        if (I == Ip) {
-          static_for<0, I + 1>(BV_CI(J) {
-            BV_CV(J);
-            const int j = J * 16 + lr;
+      for (int J = 0; J <= Ip; ++J) {
+        const int j = J * 16 + lr;
 #pragma unroll
-            for (int r = 0; r < 4; ++r)
-              if (M::row(lg, r) == rp && j < p) {
-                X[j * LDX] = acc[tix(I, J)][r];                  // w
-                if (j < m) X[j * LDX + 1] = acc[tix(I, J)][r];   // [z; 0]
-              }
-          });
-        }
-      });
+        for (int r = 0; r < 4; ++r)
+          if (M::row(lg, r) == rp && j < p) {
+            const T v = Lg[tix(Ip, J) * 256 + ln * 4 + r];
+            X[j * LDX] = v;                  // w
+            if (j < m) X[j * LDX + 1] = v;   // [z; 0]
+          }
+      }
     }
     __syncthreads();
     for (int K = Gp - 1; K >= 0; --K) {
       // publish tile row K of L (only this step indexes the tiles)
-      static_for<0, G>(BV_CI(KK) {
-        BV_CV(KK);
-        if (KK == K) {
-          static_for<0, KK + 1>(BV_CI(J) {
-            BV_CV(J);
+      for (int J = 0; J <= K; ++J)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) lrow[M::row(lg, r) * P + J * 16 + lr] = acc[tix(KK, J)][r];
-          });
-        }
-      });
+        for (int r = 0; r < 4; ++r) lrow[M::row(lg, r) * P + J * 16 + lr] = Lg[tix(K, J) * 256 + ln * 4 + r];
       {
         __syncthreads();
         if (K == Gp - 1) {
@@ -375,7 +372,9 @@ __global__ void __launch_bounds__(64) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
             x[rr] = x[rr] * rdiag[rr];
 #pragma unroll
             for (int r2 = 0; r2 < rr; ++r2) x[r2] -= lrow[rr * P + K * 16 + r2] * x[rr];
-            __builtin_amdgcn_sched_barrier(0);  // bound the live L_KK loads
+            // compiler-only memory barrier: keeps the next row's L_KK loads from being
+            // hoisted above this step (bounds the registers they occupy)
+            __asm__ volatile("" ::: "memory");
           }
 #pragma unroll
           for (int r = 0; r < 16; ++r) X[(K * 16 + r) * LDX + ln] = x[r];
@@ -413,7 +412,8 @@ __global__ void __launch_bounds__(64) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
           const T sg = cb + q == 0 ? T(1) : T(-1);
           c = M::op(sg * X[(iI + lr) * LDX + q], X[(jJ + lr) * LDX + q], c);
         }
-        const double wgt = I == J ? 1.0 : 2.0;
+        // the tile's four entries in T, then FP64 across tiles and lanes
+        T s0 = T(0), s1 = T(0), s2 = T(0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = iI + M::row(lg, r), j = jJ + lr;
@@ -424,12 +424,15 @@ __global__ void __launch_bounds__(64) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
             const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
             T rho, drho;
             mc.rho_drange(x, irange, rho, drho);
-            const double wv = wgt * (double)c[r];
-            g0 += wv * (double)rho;
-            g1 += wv * (double)drho;
-            if (i == j) g2 += (double)c[r];
+            s0 += c[r] * rho;
+            s1 += c[r] * drho;
+            if (i == j) s2 += c[r];
           }
         }
+        const double wgt = I == J ? 1.0 : 2.0;
+        g0 += wgt * (double)s0;
+        g1 += wgt * (double)s1;
+        g2 += (double)s2;
       }
   }
 #pragma unroll

@@ -1,0 +1,150 @@
+"""Summaries of rocprofv3 output for the block Vecchia kernels.
+
+Kernel durations come from a ``rocprofv3 --kernel-trace --stats
+--output-format csv`` run; HBM traffic from two ``rocprofv3 --pmc`` runs (one
+with FETCH_SIZE, one with WRITE_SIZE, both in KiB per dispatch) of a program
+that also performs a plain device copy of known size.  The copy's readings
+calibrate the counters: bytes = counter * (known copy bytes / copy reading).
+
+    python -m paper_2410_04477_amd.profiling kernels <kernel_trace.csv> --title T --command C
+    python -m paper_2410_04477_amd.profiling traffic <fetch.csv> <write.csv> --kernel REGEX \
+        --copy-bytes B --sha S --out profiles/hbm_traffic.json
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import json
+import re
+import sys
+from collections import defaultdict
+
+
+def _col(header, *keys):
+    low = [h.lower() for h in header]
+    for k in keys:
+        for i, h in enumerate(low):
+            if h == k:
+                return i
+    for k in keys:
+        for i, h in enumerate(low):
+            if k in h:
+                return i
+    raise KeyError(f"none of {keys} in {header}")
+
+
+def _rows(path):
+    with open(path, newline="") as fh:
+        r = csv.reader(fh)
+        header = next(r)
+        return header, list(r)
+
+
+def kernel_table(trace_csv: str, title: str, command: str, top: int = 30) -> str:
+    """Markdown table of per-kernel dispatch durations from a kernel-trace CSV."""
+    header, rows = _rows(trace_csv)
+    iname = _col(header, "kernel_name")
+    i0 = _col(header, "start_timestamp")
+    i1 = _col(header, "end_timestamp")
+    agg = defaultdict(list)
+    for row in rows:
+        agg[row[iname]].append(int(row[i1]) - int(row[i0]))
+    tot = sum(sum(v) for v in agg.values())
+    out = [f"# {title}", "", "Command (from the repository root; `$R` is the repository path):", "",
+           f"    {command}", "",
+           "Kernel dispatch durations from the kernel trace (every dispatch of the run, setup included).", "",
+           "| calls | avg us | min us | max us | total ms | % | kernel |", "|---:|---:|---:|---:|---:|---:|---|"]
+    for name, d in sorted(agg.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        short = name.replace("|", "/")
+        if len(short) > 96:
+            short = short[:96] + "..."
+        out.append(f"| {len(d)} | {sum(d) / len(d) / 1e3:.1f} | {min(d) / 1e3:.1f} | {max(d) / 1e3:.1f} | "
+                   f"{sum(d) / 1e6:.2f} | {100.0 * sum(d) / tot:.1f} | `{short}` |")
+    return "\n".join(out) + "\n"
+
+
+def counter_per_dispatch(pmc_csv: str, counter: str, kernel_regex: str):
+    """Mean and count of one counter over the dispatches whose kernel name
+    matches ``kernel_regex`` (values summed over the counter's instances per
+    dispatch)."""
+    header, rows = _rows(pmc_csv)
+    iname = _col(header, "kernel_name")
+    idisp = _col(header, "dispatch_id", "correlation_id")
+    icn = _col(header, "counter_name")
+    icv = _col(header, "counter_value")
+    pat = re.compile(kernel_regex)
+    per = defaultdict(float)
+    for row in rows:
+        if row[icn] == counter and pat.search(row[iname]):
+            per[row[idisp]] += float(row[icv])
+    vals = list(per.values())
+    return (sum(vals) / len(vals) if vals else float("nan")), len(vals)
+
+
+COPY_REGEX = r"elementwise|copy|Copy"
+
+
+def traffic(fetch_csv: str, write_csv: str, kernel_regex: str, copy_bytes: float, copy_regex: str = COPY_REGEX):
+    """HBM bytes per launch of the matched kernel, counters calibrated on the copy."""
+    f_k, nf = counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel_regex)
+    w_k, nw = counter_per_dispatch(write_csv, "WRITE_SIZE", kernel_regex)
+    # the calibration copy is the largest dispatch of a copy kernel in each run
+    def largest(path, counter):
+        header, rows = _rows(path)
+        iname, icn, icv = _col(header, "kernel_name"), _col(header, "counter_name"), _col(header, "counter_value")
+        idisp = _col(header, "dispatch_id", "correlation_id")
+        per = defaultdict(float)
+        pat = re.compile(copy_regex)
+        for row in rows:
+            if row[icn] == counter and pat.search(row[iname]) and not re.search(kernel_regex, row[iname]):
+                per[row[idisp]] += float(row[icv])
+        return max(per.values()) if per else float("nan")
+    cf = largest(fetch_csv, "FETCH_SIZE")
+    cw = largest(write_csv, "WRITE_SIZE")
+    half = copy_bytes / 2.0        # the copy reads and writes copy_bytes / 2 each
+    kf = half / (cf * 1024.0)
+    kw = half / (cw * 1024.0)
+    return {"fetch_kib_per_dispatch": f_k, "write_kib_per_dispatch": w_k, "dispatches": [nf, nw],
+            "copy_fetch_kib": cf, "copy_write_kib": cw, "fetch_scale": kf, "write_scale": kw,
+            "bytes_per_launch": f_k * 1024.0 * kf + w_k * 1024.0 * kw}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    k = sub.add_parser("kernels")
+    k.add_argument("trace_csv")
+    k.add_argument("--title", required=True)
+    k.add_argument("--command", required=True)
+    t = sub.add_parser("traffic")
+    t.add_argument("fetch_csv")
+    t.add_argument("write_csv")
+    t.add_argument("--kernel", required=True, help="regex of the kernel name")
+    t.add_argument("--name", required=True, help="key under which the result is stored")
+    t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--sha", required=True)
+    t.add_argument("--command", default="")
+    t.add_argument("--out", required=True)
+    a = ap.parse_args(argv)
+    if a.cmd == "kernels":
+        sys.stdout.write(kernel_table(a.trace_csv, a.title, a.command))
+        return 0
+    res = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes)
+    try:
+        with open(a.out) as fh:
+            doc = json.load(fh)
+    except (OSError, ValueError):
+        doc = {}
+    if doc.get("kernel_source_sha") != a.sha:
+        doc = {}
+    doc["kernel_source_sha"] = a.sha
+    doc["command"] = a.command
+    doc[a.name] = res
+    with open(a.out, "w") as fh:
+        json.dump(doc, fh, indent=1)
+    print(json.dumps(res))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())
