@@ -45,3 +45,26 @@ def test_status_strings_and_version_without_gpu():
 def test_binding_signatures_cover_header():
     from paper_2410_04477_amd import _lib as L
     assert set(declared_functions()) <= set(L.SIGNATURES)
+
+
+def test_fp32_wave_kernels_keep_their_tiles_in_registers():
+    """The build records each kernel's register use (compiler resource remarks).
+    No FP32 one-wave kernel may spill (its tiles would go through scratch), and
+    the FP32 classes up to G = 9 must keep two waves per SIMD."""
+    import json
+    import re
+    path = os.path.join(ROOT, "paper_2410_04477_amd", "_build", "kernel_resources.json")
+    if not os.path.exists(path):
+        pytest.skip("library not built")
+    res = json.load(open(path))
+    seen = 0
+    for name, r in res.items():
+        mt = re.search(r"bv_wave_kernelIfLi(\d+)ELi(\d)E", name)
+        if not mt:
+            continue
+        seen += 1
+        g = int(mt.group(1))
+        assert r["scratch"] == 0, (name, r)
+        if g <= 9:
+            assert r["occupancy"] >= 2, (name, r)
+    assert seen == 22   # G = 1..11, value and adjoint
