@@ -153,31 +153,41 @@ def main() -> int:
     lsz, msz = np.diff(bp), np.diff(npt)
     psz = lsz + msz
     sched = plan.schedule().cpu().numpy()
-    qdom = int(np.argmax([ms for ms, _ in kt]))
-    ms_dom, n_dom = kt[qdom]
-    cfg_dom = plan.buckets()[qdom][0]
-    off0, off1 = int(plan.c.bucket_off[qdom]), int(plan.c.bucket_off[qdom + 1])
-    blk = sched[off0:off1]
-    flops_launch = float(np.sum(step_flops(psz[blk].astype(np.float64), msz[blk].astype(np.float64),
-                                           lsz[blk].astype(np.float64))))
-    avg_launch_s = ms_dom / n_dom / 1e3
-    achieved = flops_launch / avg_launch_s
-    R, G = api.tile_config(cfg_dom, plan.engine)
-    kname = {"mfma": f"bv_wave_kernel<float,{G},1>", "mfma_wg": f"bv_mfma_kernel<float,{G},1>"}.get(
-        plan.engine, f"bv_adj_kernel<float,{R},{G},0>")
+    # the size classes run concurrently on the plan's streams: the roofline is
+    # taken over their common span (first class launch to last), per call
+    classes = plan.buckets()
+    span_ms, span_n = kt[len(classes)]
+    avg_span_s = span_ms / span_n / 1e3
+    names, cls = [], []
+    flops_launch = 0.0
+    for q, (cfg, nb) in enumerate(classes):
+        off0, off1 = int(plan.c.bucket_off[q]), int(plan.c.bucket_off[q + 1])
+        blk = sched[off0:off1]
+        fq = float(np.sum(step_flops(psz[blk].astype(np.float64), msz[blk].astype(np.float64),
+                                     lsz[blk].astype(np.float64))))
+        flops_launch += fq
+        R, G = api.tile_config(cfg, plan.engine)
+        kn = {"mfma": f"bv_wave_kernel<float,{G},1>", "mfma_wg": f"bv_mfma_kernel<float,{G},1>"}.get(
+            plan.engine, f"bv_adj_kernel<float,{R},{G},0>")
+        names.append(kn)
+        cls.append({"kernel": kn, "blocks": int(nb), "flops": fq, "ms_per_step": kt[q][0] / args.steps})
+    achieved = flops_launch / avg_span_s
     traffic = None
     tpath = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tr = json.load(fh)
-        ent = tr.get(kname)
-        if ent and tr.get("kernel_source_sha") == kernel_source_sha():
-            traffic = ent.get("bytes_per_launch")
+        if tr.get("kernel_source_sha") == kernel_source_sha() and all(n in tr for n in names):
+            traffic = float(sum(tr[n]["bytes_per_launch"] for n in names))
     roofline = {"bound": "alu" if plan.engine == "tiles" else "mfma", "achieved": achieved / 1e12,
                 "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
-                "kernel": kname, "blocks_per_launch": int(blk.size),
-                "avg_launch_ms": avg_launch_s * 1e3, "flops_per_launch": flops_launch,
-                "share_of_step": ms_dom / (1e3 * gpu_s) if gpu_s > 0 else None}
+                "kernel": f"{names[0].split('<')[0]}<float,G,...> over {len(names)} concurrent size classes "
+                          f"({', '.join(names)})",
+                "launch": "span of one call's concurrent size-class launches (first start to last end)",
+                "avg_launch_ms": avg_span_s * 1e3, "flops_per_launch": flops_launch,
+                "blocks_per_launch": int(sum(c["blocks"] for c in cls)),
+                "share_of_step": avg_span_s / (gpu_s / args.steps) if gpu_s > 0 else None,
+                "size_classes": cls}
     total_flops_step = float(np.sum(step_flops(psz.astype(np.float64), msz.astype(np.float64),
                                                lsz.astype(np.float64))))
 

@@ -183,6 +183,8 @@ typedef struct {
   void* aux_ws;
   int32_t bucket_lmax[VECCHIA_MAX_BUCKETS];  /* largest l_i of each class */
   int32_t lds_bytes;                          /* device LDS limit per workgroup */
+  int32_t bucket_main;                        /* class with the most blocks */
+  void* exec;      /* side streams and events of concurrent size classes (vecchia_plan_destroy) */
 } vecchia_plan;
 
 size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
@@ -195,13 +197,20 @@ int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, const int32_
                       int64_t n, int64_t bc, int32_t max_theta, int32_t engine,
                       void* workspace, size_t ws_bytes, void* stream);
 int vecchia_plan_attach_aux(vecchia_plan* plan, void* aux_workspace, size_t bytes);
+/* Releases what vecchia_plan_init created on the host side (side streams,
+ * events, timing records); call it before re-initialising or dropping a plan.
+ * The workspaces stay the caller's. */
+int vecchia_plan_destroy(vecchia_plan* plan);
 
 /* Per-launch timing for benchmarks.  When enabled, vecchia_loglik and
  * vecchia_loglik_grad bracket every size-class kernel launch with hipEvents
  * recorded on the call's stream (host-side objects; no device memory).
  * vecchia_plan_timing synchronises those events and returns, per size class
  * q < plan->nbuckets, the summed milliseconds of its main kernel launches and
- * their count; reset != 0 clears the record.  Disabling frees the events. */
+ * their count, and at index plan->nbuckets the summed span from the first
+ * class launch to the last of each call (the classes run concurrently on the
+ * plan's side streams), so ms and launches need nbuckets + 1 entries;
+ * reset != 0 clears the record.  Disabling frees the events. */
 int vecchia_plan_set_timing(vecchia_plan* plan, int enable);
 int vecchia_plan_timing(vecchia_plan* plan, double* ms, int64_t* launches, int reset);
 

@@ -34,7 +34,8 @@ class Plan(ctypes.Structure):
                 ("off_grad", ctypes.c_size_t), ("timing", ctypes.c_void_p), ("engine", ctypes.c_int32),
                 ("nlarge", ctypes.c_int64), ("large_slots", ctypes.c_int32), ("large_slot_elems", ctypes.c_int64),
                 ("aux_ws_bytes", ctypes.c_size_t), ("aux_ws", ctypes.c_void_p),
-                ("bucket_lmax", ctypes.c_int32 * MAX_BUCKETS), ("lds_bytes", ctypes.c_int32)]
+                ("bucket_lmax", ctypes.c_int32 * MAX_BUCKETS), ("lds_bytes", ctypes.c_int32),
+                ("bucket_main", ctypes.c_int32), ("exec", ctypes.c_void_p)]
 
 
 class VecchiaError(RuntimeError):
@@ -67,6 +68,7 @@ SIGNATURES = {
     "vecchia_adam": (ctypes.c_int, [P, P, P, P, I64, D, D, D, D, I64, P]),
     "vecchia_tile_config": (ctypes.c_int, [I32, I32, P, P]),
     "vecchia_plan_attach_aux": (ctypes.c_int, [P, P, SZ]),
+    "vecchia_plan_destroy": (ctypes.c_int, [P]),
     "vecchia_plan_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
     "vecchia_plan_timing": (ctypes.c_int, [P, P, P, ctypes.c_int]),
 }

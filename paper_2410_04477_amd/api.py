@@ -132,6 +132,14 @@ class Plan:
                     "vecchia_plan_attach_aux")
         self.block_ptr, self.nbr_ptr = block_ptr, nbr_ptr
 
+    def __del__(self):
+        # side streams and events of the concurrent size classes
+        try:
+            if getattr(self, "c", None) is not None and self.c.exec:
+                L.lib().vecchia_plan_destroy(ctypes.byref(self.c))
+        except Exception:
+            pass
+
     @property
     def bc(self) -> int:
         return int(self.c.bc)
@@ -148,12 +156,13 @@ class Plan:
         L.check(L.lib().vecchia_plan_set_timing(ctypes.byref(self.c), 1 if enable else 0), "vecchia_plan_set_timing")
 
     def timing(self, reset: bool = True):
-        """Per size class: (summed ms of the main kernel launches, launch count)."""
+        """Per size class: (summed ms of the main kernel launches, launch count),
+        followed by the summed span of the concurrent class launches per call."""
         nb = int(self.c.nbuckets)
-        ms = (ctypes.c_double * max(nb, 1))()
-        cnt = (ctypes.c_int64 * max(nb, 1))()
+        ms = (ctypes.c_double * (nb + 1))()
+        cnt = (ctypes.c_int64 * (nb + 1))()
         L.check(L.lib().vecchia_plan_timing(ctypes.byref(self.c), ms, cnt, 1 if reset else 0), "vecchia_plan_timing")
-        return [(float(ms[q]), int(cnt[q])) for q in range(nb)]
+        return [(float(ms[q]), int(cnt[q])) for q in range(nb + 1)]
 
     def schedule(self) -> torch.Tensor:
         """Block ids grouped by size class (device int32 view into the plan workspace)."""

@@ -77,6 +77,16 @@ bool theta_to_dev(const vecchia_theta& t, int d, ThetaDev& o) {
 }
 
 template <typename P> P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(base) + off); }
+
+// Side streams (default priority) on which the size classes other than the
+// largest run concurrently with it; forked from and joined back to the
+// caller's stream with events.
+constexpr int kSideStreams = 3;
+struct Exec {
+  hipStream_t side[kSideStreams] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSideStreams] = {};
+};
 }  // namespace
 
 extern "C" int vecchia_tile_config(int32_t engine, int32_t cfg, int32_t* R, int32_t* G) {
@@ -132,9 +142,31 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
     // a block with no points, or larger than even the global-workspace kernel takes
     return hmax[0] > 16383 ? VECCHIA_EUNSUPPORTED : VECCHIA_EINVAL;
   }
+  const int ncfg = engine == kEngineTiles ? kNumCfgs : kMfmaMaxG;
+  // merge sparse size classes upward: a class's kernel also takes every smaller
+  // block, and a launch of a few blocks costs a whole block's latency
+  int remap[32];
+  for (int c = 0; c < 32; ++c) remap[c] = c;
+  bool merged = false;
+  for (int c = 0; c < ncfg; ++c) {
+    if (hcounts[c] <= 0 || hcounts[c] >= kMergeBelow) continue;
+    int c2 = c + 1;
+    while (c2 < ncfg && hcounts[c2] == 0) ++c2;
+    if (c2 >= ncfg) continue;
+    hcounts[c2] += hcounts[c];
+    hlmax[c2] = hlmax[c2] > hlmax[c] ? hlmax[c2] : hlmax[c];
+    hcounts[c] = 0;
+    for (int c0 = 0; c0 <= c; ++c0)
+      if (remap[c0] == c) remap[c0] = c2;
+    merged = true;
+  }
+  if (merged) {
+    int* remap_d = at<int>(workspace, L.chunk + 384);
+    VCHECK_HIP(hipMemcpyAsync(remap_d, remap, sizeof(remap), hipMemcpyHostToDevice, s));
+    VCHECK_HIP(launch_remap(cfg_of, (int)bc, remap_d, s));
+  }
   int hoff[32] = {0};
   int acc = 0, nb = 0;
-  const int ncfg = engine == kEngineTiles ? kNumCfgs : kMfmaMaxG;
   for (int c = 0; c < ncfg; ++c) {
     hoff[c] = acc;
     if (hcounts[c] > 0) {
@@ -199,6 +231,19 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   VCHECK_HIP(hipGetDevice(&dev));
   VCHECK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
   plan->lds_bytes = lds;
+  int big = 0;
+  for (int q = 1; q < nb; ++q)
+    if (plan->bucket_off[q + 1] - plan->bucket_off[q] > plan->bucket_off[big + 1] - plan->bucket_off[big]) big = q;
+  plan->bucket_main = big;
+  if (nb > 1) {
+    Exec* ex = new Exec();
+    plan->exec = ex;
+    VCHECK_HIP(hipEventCreateWithFlags(&ex->fork, hipEventDisableTiming));
+    for (int k = 0; k < kSideStreams; ++k) {
+      VCHECK_HIP(hipStreamCreateWithFlags(&ex->side[k], hipStreamNonBlocking));
+      VCHECK_HIP(hipEventCreateWithFlags(&ex->join[k], hipEventDisableTiming));
+    }
+  }
   return VECCHIA_OK;
 }
 
@@ -231,22 +276,28 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 // 1: value + gradient.  VECCHIA_EUNSUPPORTED when the four-wave adjoint's
 // right-hand sides do not fit the device LDS.
 static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mode, AdjArgs a, const ThetaPack& thp,
-                             int grid, hipStream_t s) {
+                             int grid, hipStream_t s, void* tiles, size_t tile_bytes) {
   const int g = plan->bucket_cfg[q] + 1;
   if (plan->engine == kEngineMfma && wave_fits(g, fp32)) {
     if (mode == 0) {
       VCHECK_HIP(launch_wave(g, fp32, 0, a, thp, grid, s));
       return VECCHIA_OK;
     }
-    // adjoint: as many work items per launch as the tile buffer holds
+    // adjoint: as many work items per launch as its part of the tile buffer holds
     const size_t per = wave_tile_bytes(g, fp32);
-    const size_t cap = plan->aux_ws_bytes / per;
+    const size_t cap = tile_bytes / per;
     if (cap == 0) return VECCHIA_ENOMEM;
     const int chunk = cap < (size_t)grid ? (int)cap : grid;
-    a.tiles = plan->aux_ws;
+    a.tiles = tiles;
     for (int w0 = 0; w0 < grid; w0 += chunk) {
       a.item_base = w0;
-      VCHECK_HIP(launch_wave(g, fp32, 1, a, thp, grid - w0 < chunk ? grid - w0 : chunk, s));
+      const int n = grid - w0 < chunk ? grid - w0 : chunk;
+      if (wave_split(g, fp32)) {
+        VCHECK_HIP(launch_wave(g, fp32, 2, a, thp, n, s));
+        VCHECK_HIP(launch_wave(g, fp32, 3, a, thp, n, s));
+      } else {
+        VCHECK_HIP(launch_wave(g, fp32, 1, a, thp, n, s));
+      }
     }
     return VECCHIA_OK;
   }
@@ -270,6 +321,29 @@ static int launch_tiles_adjoint(const vecchia_plan* plan, int q, bool fp32, AdjA
     int st_ = (x);              \
     if (st_) return st_;        \
   } while (0)
+
+// Stream of size class q: the largest class stays on the caller's stream, the
+// others go round-robin to the plan's side streams when `conc`.
+static hipStream_t class_stream(const vecchia_plan* plan, int q, hipStream_t s, bool conc) {
+  if (!conc || q == plan->bucket_main) return s;
+  const int k = (q < plan->bucket_main ? q : q - 1) % kSideStreams;
+  return static_cast<Exec*>(plan->exec)->side[k];
+}
+static hipError_t fork_streams(const vecchia_plan* plan, hipStream_t s) {
+  Exec* ex = static_cast<Exec*>(plan->exec);
+  hipError_t e = hipEventRecord(ex->fork, s);
+  for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) e = hipStreamWaitEvent(ex->side[k], ex->fork, 0);
+  return e;
+}
+static hipError_t join_streams(const vecchia_plan* plan, hipStream_t s) {
+  Exec* ex = static_cast<Exec*>(plan->exec);
+  hipError_t e = hipSuccess;
+  for (int k = 0; k < kSideStreams && e == hipSuccess; ++k) {
+    e = hipEventRecord(ex->join[k], ex->side[k]);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, ex->join[k], 0);
+  }
+  return e;
+}
 
 // -------------------------------------------------------------- timing ----
 
@@ -305,6 +379,25 @@ void timing_clear(Timing* t) {
 }
 }  // namespace
 
+extern "C" int vecchia_plan_destroy(vecchia_plan* plan) {
+  if (!plan) return VECCHIA_EINVAL;
+  vecchia_plan_set_timing(plan, 0);
+  if (plan->exec) {
+    Exec* ex = static_cast<Exec*>(plan->exec);
+    for (int k = 0; k < kSideStreams; ++k) {
+      if (ex->side[k]) {
+        hipStreamSynchronize(ex->side[k]);
+        hipStreamDestroy(ex->side[k]);
+      }
+      if (ex->join[k]) hipEventDestroy(ex->join[k]);
+    }
+    if (ex->fork) hipEventDestroy(ex->fork);
+    delete ex;
+    plan->exec = nullptr;
+  }
+  return VECCHIA_OK;
+}
+
 extern "C" int vecchia_plan_set_timing(vecchia_plan* plan, int enable) {
   if (!plan) return VECCHIA_EINVAL;
   if (enable && !plan->timing) plan->timing = new Timing();
@@ -318,7 +411,7 @@ extern "C" int vecchia_plan_set_timing(vecchia_plan* plan, int enable) {
 
 extern "C" int vecchia_plan_timing(vecchia_plan* plan, double* ms, int64_t* launches, int reset) {
   if (!plan || !ms || !launches) return VECCHIA_EINVAL;
-  for (int q = 0; q < plan->nbuckets; ++q) {
+  for (int q = 0; q <= plan->nbuckets; ++q) {
     ms[q] = 0.0;
     launches[q] = 0;
   }
@@ -422,23 +515,32 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
     a.fp32_guard = precision == VECCHIA_FP32_BULK_FORCE_REFACTOR ? 2 : (fp32 ? 1 : 0);
     a.partial = part;
     a.flag = flag;
-    for (int q = 0; q < plan->nbuckets; ++q) {
+    const bool conc = plan->exec != nullptr;   // size classes run concurrently
+    TimingRec span;
+    VCHECK_HIP(time_begin(plan, plan->nbuckets, s, span));
+    if (conc) VCHECK_HIP(fork_streams(plan, s));
+    // largest blocks first: their long single-wave items start early and the
+    // smaller classes fill in around them
+    for (int q = plan->nbuckets - 1; q >= 0; --q) {
       const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+      const hipStream_t sq = class_stream(plan, q, s, conc);
       a.sched = sched + plan->bucket_off[q];
       a.nsched = ns;
       TimingRec tr;
-      VCHECK_HIP(time_begin(plan, q, s, tr));
+      VCHECK_HIP(time_begin(plan, q, sq, tr));
       if (plan->bucket_cfg[q] == kLargeCfg) {
         const int g = ns * nt < plan->large_slots ? ns * nt : plan->large_slots;
-        VCHECK_HIP(launch_large(fp32, as_large(a, plan), thp, g, s));
+        VCHECK_HIP(launch_large(fp32, as_large(a, plan), thp, g, sq));
       } else {
         if (plan->engine == kEngineTiles)
-          VCHECK_HIP(launch_forward(plan->bucket_cfg[q], fp32, a, thp, ns * nt, s));
+          VCHECK_HIP(launch_forward(plan->bucket_cfg[q], fp32, a, thp, ns * nt, sq));
         else
-          VCHECK_ST(launch_mfma_class(plan, q, fp32, 0, as_adj(a, plan), thp, ns * nt, s));
+          VCHECK_ST(launch_mfma_class(plan, q, fp32, 0, as_adj(a, plan), thp, ns * nt, sq, nullptr, 0));
       }
-      VCHECK_HIP(time_end(plan, s, tr));
+      VCHECK_HIP(time_end(plan, sq, tr));
     }
+    if (conc) VCHECK_HIP(join_streams(plan, s));
+    VCHECK_HIP(time_end(plan, s, span));
     if (fp32) {
       // FP32 guard: compact flagged (theta, block) pairs per size class, re-run them in FP64
       VCHECK_HIP(launch_fill_int(count, plan->nbuckets, 0, s));
@@ -460,7 +562,7 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
         else if (plan->engine == kEngineTiles)
           VCHECK_HIP(launch_forward(plan->bucket_cfg[q], false, r, thp, cap < 256 ? cap : 256, s));
         else
-          VCHECK_ST(launch_mfma_class(plan, q, false, 0, as_adj(r, plan), thp, cap, s));
+          VCHECK_ST(launch_mfma_class(plan, q, false, 0, as_adj(r, plan), thp, cap, s, nullptr, 0));
       }
     }
     VCHECK_HIP(launch_reduce_partials(part, flag, bc, nt, fp32 ? 0 : 1, loglik + t0,
@@ -515,18 +617,39 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
     a.partial = part;
     a.gpart = gpart;
     a.flag = flag;
+    // the one-wave adjoint's tile buffer is split among the size classes so
+    // that they can run concurrently; if it is too small they run in turn
+    size_t off[VECCHIA_MAX_BUCKETS + 1] = {0};
     for (int q = 0; q < plan->nbuckets; ++q) {
+      const int g = plan->bucket_cfg[q] + 1;
+      const size_t ns = (size_t)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+      const bool wave = plan->engine == kEngineMfma && wave_fits(g, fp32);
+      off[q + 1] = off[q] + (wave ? ns * nt * wave_tile_bytes(g, fp32) : 0);
+    }
+    const bool conc = plan->exec != nullptr && off[plan->nbuckets] <= plan->aux_ws_bytes;
+    TimingRec span;
+    VCHECK_HIP(time_begin(plan, plan->nbuckets, s, span));
+    if (conc) VCHECK_HIP(fork_streams(plan, s));
+    // largest blocks first: their long single-wave items start early and the
+    // smaller classes fill in around them
+    for (int q = plan->nbuckets - 1; q >= 0; --q) {
       const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+      const hipStream_t sq = class_stream(plan, q, s, conc);
       a.sched = sched + plan->bucket_off[q];
       a.nsched = ns;
       TimingRec tr;
-      VCHECK_HIP(time_begin(plan, q, s, tr));
+      VCHECK_HIP(time_begin(plan, q, sq, tr));
       if (plan->engine == kEngineTiles)
-        VCHECK_ST(launch_tiles_adjoint(plan, q, fp32, a, thp, ns * nt, s));
+        VCHECK_ST(launch_tiles_adjoint(plan, q, fp32, a, thp, ns * nt, sq));
+      else if (conc)
+        VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq,
+                                    static_cast<char*>(plan->aux_ws) + off[q], off[q + 1] - off[q]));
       else
-        VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, s));
-      VCHECK_HIP(time_end(plan, s, tr));
+        VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq, plan->aux_ws, plan->aux_ws_bytes));
+      VCHECK_HIP(time_end(plan, sq, tr));
     }
+    if (conc) VCHECK_HIP(join_streams(plan, s));
+    VCHECK_HIP(time_end(plan, s, span));
     if (fp32) {
       VCHECK_HIP(launch_fill_int(count, plan->nbuckets, 0, s));
       for (int q = 0; q < plan->nbuckets; ++q) {
@@ -545,7 +668,7 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
         if (plan->engine == kEngineTiles)
           VCHECK_ST(launch_tiles_adjoint(plan, q, false, r, thp, cap < 256 ? cap : 256, s));
         else
-          VCHECK_ST(launch_mfma_class(plan, q, false, 1, r, thp, cap, s));
+          VCHECK_ST(launch_mfma_class(plan, q, false, 1, r, thp, cap, s, plan->aux_ws, plan->aux_ws_bytes));
       }
     }
     VCHECK_HIP(launch_reduce_partials(part, flag, bc, nt, fp32 ? 0 : 1, loglik + t0,

@@ -68,6 +68,8 @@ constexpr int kWaveChunk = 32;  // adjoint right-hand sides per pass (bounds the
 inline size_t wave_tile_bytes(int g, bool fp32) { return (size_t)g * (g + 1) / 2 * 256 * (fp32 ? 4 : 8); }
 constexpr size_t kAdjTileCap = (size_t)4 << 30;
 bool wave_fits(int g, bool fp32);
+// gradient as two launches (factor + tiles, then the adjoint from the tiles)
+inline bool wave_split(int g, bool fp32) { return fp32 && g >= 10; }
 hipError_t launch_wave_f32(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 hipError_t launch_wave_f64(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 hipError_t launch_wave(int g, bool fp32, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
@@ -100,6 +102,9 @@ inline int mfma_ldx(int nr_max) { return 16 * ((nr_max + 15) / 16) + 1; }
 hipError_t launch_classify(const int* block_ptr, const int* nbr_ptr, int bc, int* cfg_of, int* counts,
                            unsigned long long* stats, int* maxes, int* lmax_cfg, int engine, hipStream_t s);
 hipError_t launch_scatter(const int* cfg_of, int bc, const int* cfg_off, int* cursor, int* sched, hipStream_t s);
+hipError_t launch_remap(int* cfg_of, int bc, const int* remap, hipStream_t s);
+// size classes with fewer blocks than this run with the next larger populated class
+constexpr int kMergeBelow = 256;
 hipError_t launch_fill_int(int* p, int n, int v, hipStream_t s);
 hipError_t launch_compact_flagged(const int* sched, int nsched, int ntheta, int bc, const int* flag, int* list,
                                   int* count, hipStream_t s);

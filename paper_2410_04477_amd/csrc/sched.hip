@@ -44,6 +44,14 @@ __global__ void scatter_kernel(const int* __restrict__ cfg_of, int bc, const int
   sched[cfg_off[c] + pos] = b;
 }
 
+// Size-class merge: cfg_of[b] <- remap[cfg_of[b]] (classes >= 0 only).
+__global__ void remap_kernel(int* __restrict__ cfg_of, int bc, const int* __restrict__ remap) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= bc) return;
+  const int c = cfg_of[b];
+  if (c >= 0) cfg_of[b] = remap[c];
+}
+
 __global__ void fill_int_kernel(int* __restrict__ p, int n, int v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -137,6 +145,11 @@ hipError_t launch_classify(const int* block_ptr, const int* nbr_ptr, int bc, int
 
 hipError_t launch_scatter(const int* cfg_of, int bc, const int* cfg_off, int* cursor, int* sched, hipStream_t s) {
   hipLaunchKernelGGL(scatter_kernel, dim3(cdiv(bc, 256)), dim3(256), 0, s, cfg_of, bc, cfg_off, cursor, sched);
+  return hipGetLastError();
+}
+
+hipError_t launch_remap(int* cfg_of, int bc, const int* remap, hipStream_t s) {
+  hipLaunchKernelGGL(remap_kernel, dim3(cdiv(bc, 256)), dim3(256), 0, s, cfg_of, bc, remap);
   return hipGetLastError();
 }
 

@@ -18,12 +18,14 @@
 // panel costs no cross-wave synchronisation.  Pivots d_k and border entries
 // w_k (k >= m) give log det and the quadratic form, summed in FP64.
 //
-// Adjoint (MODE 1): the finished factor columns are restored into the tiles,
-// then X = L^-T [ w | [z; 0] | [0; I_l] ] is solved tile row by tile row
-// (16-row triangular solve per right-hand side, MFMA updates of the rows
-// above), and W = alpha alpha^T - b b^T - X_R X_R^T is formed tile by tile with
-// MFMA and contracted against dK regenerated entry by entry (FP64 sums):
-// d l_i = 1/2 <W, dK>.
+// Adjoint (MODE 1): the factor tiles go to the item's slot of a global tile
+// buffer and leave the registers.  The diagonal 16 x 16 blocks of L are
+// inverted (16 lanes per block, four blocks at a time) and written back, so
+// that X = L^-T [ w | [z; 0] | [0; I_l] ] is pure MFMA work tile row by tile
+// row: X_K <- inv(L_KK)^T X_K, then X_J -= L_KJ^T X_K for the rows above, with
+// the A operands read straight from the buffer.  W = alpha alpha^T - b b^T -
+// X_R X_R^T is formed tile by tile with MFMA and contracted against dK
+// regenerated entry by entry (FP64 across tiles): d l_i = 1/2 <W, dK>.
 #pragma once
 
 #include <utility>
@@ -63,6 +65,12 @@ template <> struct WMma<float> {
   // tile row held by accumulator register r of lane group g
   static __device__ __forceinline__ constexpr int row(int g, int r) { return 4 * g + r; }
   static __device__ __forceinline__ float rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+  // position, inside a tile stored in accumulator order (lane * 4 + register),
+  // of element (4 s + l / 16, l % 16): the A operand of lane l for k-step s
+  // when the stored tile is used transposed
+  static __device__ __forceinline__ constexpr int aop(int l, int s) { return ((l & 15) + 16 * s) * 4 + (l >> 4); }
+  // position of element (i, j) of a tile stored in accumulator order
+  static __device__ __forceinline__ constexpr int at(int i, int j) { return (j + 16 * (i >> 2)) * 4 + (i & 3); }
 };
 template <> struct WMma<double> {
   typedef w64x4_t acc;
@@ -71,35 +79,46 @@ template <> struct WMma<double> {
   }
   static __device__ __forceinline__ constexpr int row(int g, int r) { return g + 4 * r; }
   static __device__ __forceinline__ double rsqrt(double x) { return 1.0 / sqrt(x); }
+  static __device__ __forceinline__ constexpr int aop(int l, int s) { return l * 4 + s; }
+  static __device__ __forceinline__ constexpr int at(int i, int j) { return (j + 16 * (i & 3)) * 4 + (i >> 2); }
 };
 
 // lower-triangular tile (I, J), J <= I, in row-major packed order
 __host__ __device__ constexpr int tix(int I, int J) { return I * (I + 1) / 2 + J; }
 
+constexpr int kStageStride = 260;   // staged 16 x 16 tiles, padded so four tiles fall in different banks
+
 __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
-  // su (3 P), sy, sdk, swk (P each), then the panel (4 P) or, for the adjoint,
-  // one chunk of right-hand sides (P x (kWaveChunk + 1)), a published tile
-  // row of L (16 x P) and the reciprocals of its diagonal (16)
-  return 6 * 16 * G + (mode == 0 ? 4 * 16 * G : 16 * G * (kWaveChunk + 1) + 16 * 16 * G + 16);
+  // su (3 P) for the whole kernel, then a work region: the panel (4 P) and sy,
+  // sdk, swk (P each) during the factorisation; for the adjoint, one chunk of
+  // right-hand sides (P x (kWaveChunk + 1)) or four staged diagonal tiles
+  return 3 * 16 * G + (mode == 0 || mode == 2 ? 7 * 16 * G
+                                 : (16 * G * (kWaveChunk + 1) > 7 * 16 * G
+                                        ? (16 * G * (kWaveChunk + 1) > 4 * kStageStride ? 16 * G * (kWaveChunk + 1)
+                                                                                     : 4 * kStageStride)
+                                        : 7 * 16 * G));
 }
 
 // Two waves per SIMD where the register file holds them without spilling
-// (FP32 up to G = 9); one otherwise.
-template <typename T, int G>
-constexpr int wave_min_waves() { return sizeof(T) == 4 && G <= 9 ? 2 : 1; }
-
+// (FP32 up to G = 9, and the FP32 adjoint-only kernels); one otherwise.
 template <typename T, int G, int MODE>
-__global__ void __launch_bounds__(64, (wave_min_waves<T, G>())) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
+constexpr int wave_min_waves() { return sizeof(T) == 4 && (G <= 9 || MODE == 3) ? 2 : 1; }
+
+// Modes: 0 value; 1 value and gradient in one launch; 2 value and the factor
+// tiles to the tile buffer; 3 gradient from those tiles (a second launch that
+// holds no tiles in registers, so it runs more waves per SIMD than mode 1).
+template <typename T, int G, int MODE>
+__global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
   constexpr int P = 16 * G;
   constexpr int NT = G * (G + 1) / 2;
   typedef WMma<T> M;
   typedef typename M::acc acc_t;
   extern __shared__ __align__(16) unsigned char smem[];
   T* su = reinterpret_cast<T*>(smem);  // scaled coordinates relative to the block's first point, su[k * P + i]
-  T* sy = su + 3 * P;                  // border row y_J
+  T* work = su + 3 * P;
+  T* sy = work + 4 * P;                // border row y_J
   T* sdk = sy + P;                     // pivots d_k
   T* swk = sdk + P;                    // border entries w_k
-  T* work = swk + P;
 
   const int ln = threadIdx.x, lr = ln & 15, lg = ln >> 4;
   const int total = a.list ? *a.list_count : a.nsched * a.ntheta;
@@ -122,19 +141,24 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G>())) bv_wave_kernel(A
   for (int i = ln; i < P; i += 64) {
     if (i < p) {
       const int g = (i < m) ? a.nbr_idx[n0 + i] : (b0 + i - m);
-      sy[i] = T(a.y[g]);
+      if (MODE != 3) sy[i] = T(a.y[g]);
       for (int k = 0; k < 3; ++k)
         su[k * P + i] = k < a.d ? T((a.locs[(size_t)g * a.d + k] - a.locs[(size_t)b0 * a.d + k]) * th.inv_scale[k]) : T(0);
     } else {
-      sy[i] = T(0);
+      if (MODE != 3) sy[i] = T(0);
       for (int k = 0; k < 3; ++k) su[k * P + i] = T(0);
     }
   }
   __syncthreads();
+  const size_t o = (size_t)tt * a.bc + b;
+  T* Lg = reinterpret_cast<T*>(a.tiles) + (size_t)(wi - a.item_base) * (NT * 256);   // tile slot (MODE 1-3)
+  double acc_ll = 0.0;
+  int flag = 0;
+  const MaternCoef<T> mc(th.nu_code);
+  if constexpr (MODE != 3) {   // MODE 3 starts from the factor tiles of a MODE 2 launch
 
   // ---- generate the bordered joint matrix in the accumulator tiles ----------
   const T sig2 = T(th.sigma2), nug = T(th.nugget);
-  const MaternCoef<T> mc(th.nu_code);
   acc_t acc[NT];
   static_for<0, G>(BV_CI(I) {
     BV_CV(I);
@@ -275,8 +299,6 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G>())) bv_wave_kernel(A
   const double guard = a.fp32_guard == 2 ? INFINITY
       : a.fp32_guard ? fmax(0.5 * th.nugget, (double)p * 1.1920928955078125e-07 * (th.sigma2 + th.nugget))
       : 0.0;
-  double acc_ll = 0.0;
-  int flag = 0;
   for (int k = ln; k < p; k += 64) {
     const double dd = (double)sdk[k];
     if (!(dd > guard)) flag |= a.fp32_guard ? 1 : 2;
@@ -291,34 +313,85 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G>())) bv_wave_kernel(A
     acc_ll += __shfl_down(acc_ll, off, 64);
     flag |= __shfl_down(flag, off, 64);
   }
-  const size_t o = (size_t)tt * a.bc + b;
-  if (MODE == 0) {
+  if (MODE == 0 || MODE == 2) {
     if (ln == 0) {
       a.partial[o] = (flag & 2) && !a.fp32_guard ? __builtin_nan("") : -0.5 * (acc_ll + (double)l * kLog2Pi);
       a.flag[o] = flag | a.flag_or;
     }
-    return;
   }
+  if (MODE == 0) return;
   // the factor leaves the registers for this item's slot of the tile buffer
-  // (accumulator order, 256 elements per tile); the adjoint reads it back one
-  // tile row at a time, so its phases do not hold the tiles in registers
-  T* Lg = reinterpret_cast<T*>(a.tiles) + (size_t)(wi - a.item_base) * (NT * 256);
+  // (accumulator order, 256 elements per tile), so the adjoint's phases do not
+  // hold the tiles in registers
   static_for<0, NT>(BV_CI(t) {
     BV_CV(t);
 #pragma unroll
     for (int r = 0; r < 4; ++r) Lg[t * 256 + ln * 4 + r] = acc[t][r];
   });
   __syncthreads();
+  if (MODE == 2) return;
+  } else {
+    flag = a.flag[o];   // written by the factorisation launch
+  }
 
-  // ---- adjoint: X <- L^-T X and the contraction, kWaveChunk right-hand sides at a time
-  // (the factor stays in the tiles, so a chunk only repeats the triangular solves)
   constexpr int LDX = kWaveChunk + 1;
+  constexpr int GM = G > 1 ? G - 1 : 1;   // tile rows above a diagonal step, at most
   const int nr = l + 2;
-  T* X = work;               // X[row * LDX + col], one chunk of right-hand sides
-  T* lrow = work + P * LDX;  // published tile row of L, lrow[r * P + col]
-  T* rdiag = lrow + 16 * P;  // reciprocals of its diagonal
   const int Ip = p >> 4, rp = p & 15;
   const int Gp = (p + 15) >> 4;
+  T* X = work;   // X[row * LDX + col], one chunk of right-hand sides
+
+  // border row p of the bordered factor: w = L^-1 y_J (read before the
+  // diagonal tiles are replaced by their inverses)
+  constexpr int NW = (P + 63) / 64;
+  T wreg[NW];
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const int j = ln + 64 * k;
+    wreg[k] = j < p ? Lg[(Ip * (Ip + 1) / 2 + (j >> 4)) * 256 + M::at(rp, j & 15)] : T(0);
+  }
+
+  // ---- inverses of the diagonal 16 x 16 blocks of L, four at a time ----------
+  // lane (c = l % 16, g = l / 16) forms column c of inv(L_KK), K = K0 + g, by
+  // forward substitution; the border row and the padding are identity rows
+  for (int K0 = 0; K0 < Gp; K0 += 4) {
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      const int K = K0 + g;
+      if (K < Gp) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int rw = M::row(lg, r);
+          const int i = K * 16 + rw, j = K * 16 + lr;
+          T v = Lg[(K * (K + 1) / 2 + K) * 256 + ln * 4 + r];
+          if (i >= p || j >= p) v = (i == j) ? T(1) : T(0);
+          X[g * kStageStride + rw * 16 + lr] = v;
+        }
+      }
+    }
+    __syncthreads();
+    const int K = K0 + lg;
+    if (K < Gp) {
+      const T* Lk = X + lg * kStageStride;
+      const int c = lr;
+      T x[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        T sum = T(0);
+#pragma unroll
+        for (int k = 0; k < i; ++k) sum += Lk[i * 16 + k] * x[k];
+        const T rd = T(1) / Lk[i * 16 + i];
+        x[i] = i < c ? T(0) : (i == c ? rd : -sum * rd);
+      }
+      T* dst = Lg + (K * (K + 1) / 2 + K) * 256;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) dst[M::at(i, c)] = x[i];
+    }
+  }
+  __syncthreads();
+
+  // ---- X <- L^-T X and the contraction, kWaveChunk right-hand sides per pass --
   const T irange = T(th.inv_range);
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
   for (int cb = 0; cb < nr; cb += kWaveChunk) {
@@ -331,96 +404,126 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G>())) bv_wave_kernel(A
     for (int c = ln; c < nc; c += 64)
       if (cb + c >= 2) X[(m + cb + c - 2) * LDX + c] = T(1);
     if (cb == 0) {
-      for (int J = 0; J <= Ip; ++J) {
-        const int j = J * 16 + lr;
 #pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (M::row(lg, r) == rp && j < p) {
-            const T v = Lg[tix(Ip, J) * 256 + ln * 4 + r];
-            X[j * LDX] = v;                  // w
-            if (j < m) X[j * LDX + 1] = v;   // [z; 0]
-          }
+      for (int k = 0; k < NW; ++k) {
+        const int j = ln + 64 * k;
+        if (j < p) {
+          X[j * LDX] = wreg[k];
+          if (j < m) X[j * LDX + 1] = wreg[k];
+        }
       }
     }
     __syncthreads();
     for (int K = Gp - 1; K >= 0; --K) {
-      // publish tile row K of L (only this step indexes the tiles)
-      for (int J = 0; J <= K; ++J)
+      const T* Lrow = Lg + (K * (K + 1) / 2) * 256;   // tile row K: tiles (K, 0..K)
+      // A operands from the tile buffer: inv(L_KK)^T and -L_KJ^T, J < K
+      T ad[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) lrow[M::row(lg, r) * P + J * 16 + lr] = Lg[tix(K, J) * 256 + ln * 4 + r];
-      {
-        __syncthreads();
-        if (K == Gp - 1) {
-          // the tiles hold L (zeros above the diagonal) on rows and columns < p;
-          // the border row and the padding become identity rows here
-          for (int e = ln; e < 16 * (K + 1) * 16; e += 64) {
-            const int rw = e / (16 * (K + 1)), j = e - rw * 16 * (K + 1), i = K * 16 + rw;
-            if (i >= p || j >= p) lrow[rw * P + j] = (i == j) ? T(1) : T(0);
-          }
-          __syncthreads();
+      for (int sb = 0; sb < 4; ++sb) ad[sb] = Lrow[K * 256 + M::aop(ln, sb)];
+      T aj[GM][4];
+#pragma unroll
+      for (int J = 0; J < GM; ++J)
+        if (J < K) {
+#pragma unroll
+          for (int sb = 0; sb < 4; ++sb) aj[J][sb] = -Lrow[J * 256 + M::aop(ln, sb)];
         }
-        if (ln < 16) rdiag[ln] = T(1) / lrow[ln * P + K * 16 + ln];
-        __syncthreads();
-        // diagonal tile: X_K <- L_KK^-T X_K, one lane per right-hand side
-        if (ln < nc) {
-          T x[16];
+      // diagonal step: X_K <- inv(L_KK)^T X_K
+      acc_t dq[2];
 #pragma unroll
-          for (int r = 0; r < 16; ++r) x[r] = X[(K * 16 + r) * LDX + ln];
-          // column-oriented: finish x[rr], then remove it from the rows above
+      for (int q = 0; q < 2; ++q) {
 #pragma unroll
-          for (int rr = 15; rr >= 0; --rr) {
-            x[rr] = x[rr] * rdiag[rr];
+        for (int r = 0; r < 4; ++r) dq[q][r] = T(0);
+        if (q < nq) {
 #pragma unroll
-            for (int r2 = 0; r2 < rr; ++r2) x[r2] -= lrow[rr * P + K * 16 + r2] * x[rr];
-            // compiler-only memory barrier: keeps the next row's L_KK loads from being
-            // hoisted above this step (bounds the registers they occupy)
-            __asm__ volatile("" ::: "memory");
+          for (int sb = 0; sb < 4; ++sb) dq[q] = M::op(ad[sb], X[(K * 16 + 4 * sb + lg) * LDX + q * 16 + lr], dq[q]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (q < nq) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) X[(K * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = dq[q][r];
+        }
+      __syncthreads();
+      // rows above: X_J -= L_KJ^T X_K (all tiles loaded first, then the MFMA chains)
+      if (K > 0) {
+        T bq[2][4];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int sb = 0; sb < 4; ++sb) bq[q][sb] = X[(K * 16 + 4 * sb + lg) * LDX + q * 16 + lr];
+        acc_t cj[GM][2];
+#pragma unroll
+        for (int J = 0; J < GM; ++J)
+          if (J < K) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+              if (q < nq) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) cj[J][q][r] = X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr];
+              }
           }
 #pragma unroll
-          for (int r = 0; r < 16; ++r) X[(K * 16 + r) * LDX + ln] = x[r];
-        }
-        __syncthreads();
-        // rows above: X_J -= L_KJ^T X_K
-        for (int J = 0; J < K; ++J)
-          for (int q = 0; q < nq; ++q) {
-            acc_t c;
+        for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
-            for (int r = 0; r < 4; ++r) c[r] = X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr];
+          for (int J = 0; J < GM; ++J)
 #pragma unroll
-            for (int sub = 0; sub < 4; ++sub) {
-              const T av = -lrow[(4 * sub + lg) * P + J * 16 + lr];
-              const T bv = X[(K * 16 + 4 * sub + lg) * LDX + q * 16 + lr];
-              c = M::op(av, bv, c);
-            }
+            for (int q = 0; q < 2; ++q)
+              if (J < K && q < nq) cj[J][q] = M::op(aj[J][sb], bq[q][sb], cj[J][q]);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = c[r];
+        for (int J = 0; J < GM; ++J)
+          if (J < K) {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+              if (q < nq) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = cj[J][q][r];
+              }
           }
         __syncthreads();
       }
     }
 
-    // W = alpha alpha^T - b b^T - X_R X_R^T (this chunk's columns), contracted with dK
+    // W = alpha alpha^T - b b^T - X_R X_R^T (this chunk's columns), contracted with dK;
+    // the next tile's MFMA chain is issued before this tile's contraction
     const int nk = (nc + 3) >> 2;
-    for (int I = 0; I < Gp; ++I)
-      for (int J = 0; J <= I; ++J) {
+    for (int I = 0; I < Gp; ++I) {
+      T av[kWaveChunk / 4];
+#pragma unroll
+      for (int kq = 0; kq < kWaveChunk / 4; ++kq) {
+        const int q = 4 * kq + lg;
+        av[kq] = (cb + q == 0 ? T(1) : T(-1)) * X[(I * 16 + lr) * LDX + q];
+      }
+      T ri[4][3];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I * 16 + M::row(lg, r);
+        ri[r][0] = su[i];
+        ri[r][1] = su[P + i];
+        ri[r][2] = su[2 * P + i];
+      }
+      auto wtile = [&](int J) __attribute__((always_inline)) {
         acc_t c;
 #pragma unroll
         for (int r = 0; r < 4; ++r) c[r] = T(0);
-        const int iI = I * 16, jJ = J * 16;
-        for (int kq = 0; kq < nk; ++kq) {
-          const int q = 4 * kq + lg;
-          const T sg = cb + q == 0 ? T(1) : T(-1);
-          c = M::op(sg * X[(iI + lr) * LDX + q], X[(jJ + lr) * LDX + q], c);
-        }
-        // the tile's four entries in T, then FP64 across tiles and lanes
+#pragma unroll
+        for (int kq = 0; kq < kWaveChunk / 4; ++kq)
+          if (kq < nk) c = M::op(av[kq], X[(J * 16 + lr) * LDX + 4 * kq + lg], c);
+        return c;
+      };
+      acc_t cn = wtile(0);
+      for (int J = 0; J <= I; ++J) {
+        const acc_t c = cn;
+        if (J < I) cn = wtile(J + 1);
+        const int j = J * 16 + lr;
+        const T sj0 = su[j], sj1 = su[P + j], sj2 = su[2 * P + j];
         T s0 = T(0), s1 = T(0), s2 = T(0);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int i = iI + M::row(lg, r), j = jJ + lr;
+          const int i = I * 16 + M::row(lg, r);
           if (i < p && j < p) {
-            const T dx = su[i] - su[j];
-            const T dy = su[P + i] - su[P + j];
-            const T dz = su[2 * P + i] - su[2 * P + j];
+            const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
             const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
             T rho, drho;
             mc.rho_drange(x, irange, rho, drho);
@@ -434,6 +537,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G>())) bv_wave_kernel(A
         g1 += wgt * (double)s1;
         g2 += (double)s2;
       }
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
@@ -443,11 +547,13 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G>())) bv_wave_kernel(A
   }
   if (ln == 0) {
     const bool bad = (flag & 2) && !a.fp32_guard;
-    a.partial[o] = bad ? __builtin_nan("") : -0.5 * (acc_ll + (double)l * kLog2Pi);
+    if (MODE == 1) {
+      a.partial[o] = bad ? __builtin_nan("") : -0.5 * (acc_ll + (double)l * kLog2Pi);
+      a.flag[o] = flag | a.flag_or;
+    }
     a.gpart[3 * o + 0] = bad ? __builtin_nan("") : 0.5 * g0;
     a.gpart[3 * o + 1] = bad ? __builtin_nan("") : 0.5 * th.sigma2 * g1;
     a.gpart[3 * o + 2] = bad ? __builtin_nan("") : 0.5 * g2;
-    a.flag[o] = flag | a.flag_or;
   }
 }
 
@@ -460,6 +566,11 @@ static hipError_t launch_wave_g(const AdjArgs& a, const ThetaPack& thp, int grid
 
 template <typename T, int MODE>
 static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
+  if constexpr (MODE >= 2) {   // split gradient: only the classes that use it
+    if (g == 10) return launch_wave_g<T, 10, MODE>(a, thp, grid, s);
+    if (g == 11) return launch_wave_g<T, 11, MODE>(a, thp, grid, s);
+    return hipErrorInvalidValue;
+  } else {
   switch (g) {
     case 1: return launch_wave_g<T, 1, MODE>(a, thp, grid, s);
     case 2: return launch_wave_g<T, 2, MODE>(a, thp, grid, s);
@@ -473,6 +584,7 @@ static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, i
     case 10: return launch_wave_g<T, 10, MODE>(a, thp, grid, s);
     case 11: return launch_wave_g<T, 11, MODE>(a, thp, grid, s);
     default: return hipErrorInvalidValue;
+  }
   }
 }
 

@@ -63,6 +63,27 @@ def kernel_table(trace_csv: str, title: str, command: str, top: int = 30) -> str
     return "\n".join(out) + "\n"
 
 
+def concurrent_spans(trace_csv: str, kernel_regex: str):
+    """Dispatches matching ``kernel_regex`` grouped into runs of overlapping
+    intervals (the size classes of one call run concurrently); returns the
+    spans (first start to last end, ns) and the number of dispatches of each."""
+    header, rows = _rows(trace_csv)
+    iname = _col(header, "kernel_name")
+    i0 = _col(header, "start_timestamp")
+    i1 = _col(header, "end_timestamp")
+    pat = re.compile(kernel_regex)
+    iv = sorted((int(r[i0]), int(r[i1])) for r in rows if pat.search(r[iname]))
+    spans, counts = [], []
+    for a, b in iv:
+        if spans and a <= spans[-1][1]:
+            spans[-1][1] = max(spans[-1][1], b)
+            counts[-1] += 1
+        else:
+            spans.append([a, b])
+            counts.append(1)
+    return [b - a for a, b in spans], counts
+
+
 def counter_per_dispatch(pmc_csv: str, counter: str, kernel_regex: str):
     """Mean and count of one counter over the dispatches whose kernel name
     matches ``kernel_regex`` (values summed over the counter's instances per
@@ -116,6 +137,8 @@ def main(argv=None) -> int:
     k.add_argument("trace_csv")
     k.add_argument("--title", required=True)
     k.add_argument("--command", required=True)
+    k.add_argument("--span", default="", help="regex of concurrently launched kernels whose common span to report")
+    k.add_argument("--span-min-dispatches", type=int, default=2)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -128,6 +151,14 @@ def main(argv=None) -> int:
     a = ap.parse_args(argv)
     if a.cmd == "kernels":
         sys.stdout.write(kernel_table(a.trace_csv, a.title, a.command))
+        if a.span:
+            spans, counts = concurrent_spans(a.trace_csv, a.span)
+            sel = [s for s, c in zip(spans, counts) if c >= a.span_min_dispatches]
+            if sel:
+                sys.stdout.write(f"\nConcurrent span of `{a.span}` ({len(sel)} calls with >= "
+                                 f"{a.span_min_dispatches} overlapping dispatches): mean "
+                                 f"{sum(sel) / len(sel) / 1e3:.1f} us, min {min(sel) / 1e3:.1f} us, "
+                                 f"max {max(sel) / 1e3:.1f} us.\n")
         return 0
     res = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes)
     try:

@@ -81,6 +81,33 @@ def test_adjoint_many_right_hand_sides(bc, m, engine):
     assert _rel(gpart32[0].cpu().numpy(), ref) <= 1e-3
 
 
+def test_fp32_gradient_large_classes_vs_oracle():
+    """p_i + 1 in (144, 176]: the FP32 gradient of these size classes runs as two
+    launches (factorisation + tiles, then the adjoint from the tiles).  Per-block
+    FP32 terms within 1e-3 (norm-wise) of the FP64 oracle, FP32 values within
+    1e-3 per block and 1e-4 on the total; the forced-refactor path reproduces
+    FP64 exactly."""
+    th = W.Theta(1.0, 0.1, 2e-3, 1.5)
+    pb = problem("big32", 3000, 2, 150, 130, th, 81)
+    p = np.diff(pb["block_ptr"]) + np.diff(pb["nbr_ptr"])
+    assert ((p + 1 > 144) & (p + 1 <= 176)).sum() > 50
+    mod = _model(pb, 1.5)
+    assert any(cfg >= 9 for cfg, _ in mod.plan.buckets())
+    t = [mod.theta(th.sigma2, th.beta, th.nugget)]
+    ll, g, cnt, part, gpart = mod.loglik_grad(t, "fp32", True)
+    ref = _oracle_grad(pb, th)
+    big = (p + 1 > 144)
+    assert _rel(gpart[0].cpu().numpy()[big], ref[big]) <= 1e-3
+    assert _rel(gpart[0].cpu().numpy(), ref) <= 1e-3
+    rterms = np.asarray(oracle_terms(pb, th))
+    np.testing.assert_allclose(part[0].cpu().numpy(), rterms, rtol=1e-3, atol=1e-3)
+    assert abs(float(ll[0]) - rterms.sum()) <= 1e-4 * abs(rterms.sum())
+    l64, g64, _, _, _ = mod.loglik_grad(t, "fp64")
+    lf, gf, cf, _, _ = mod.loglik_grad(t, "fp32_force_refactor")
+    assert int(cf[0, 0]) == len(p)
+    assert torch.equal(g64, gf) and torch.equal(l64, lf)
+
+
 def test_adjoint_vs_central_fd_and_fp32():
     """Central differences with h = 1e-5 (absolute, natural parameters).  Their
     truncation error is O(h^2 f3) (f3 the third derivative), which grows like
