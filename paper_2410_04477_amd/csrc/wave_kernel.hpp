@@ -20,7 +20,7 @@
 //
 // Adjoint (MODE 1): the factor tiles go to the item's slot of a global tile
 // buffer and leave the registers.  The diagonal 16 x 16 blocks of L are
-// inverted (16 lanes per block, four blocks at a time) and written back, so
+// inverted (16 lanes per block, all blocks in one pass) and written back, so
 // that X = L^-T [ w | [z; 0] | [0; I_l] ] is pure MFMA work tile row by tile
 // row: X_K <- inv(L_KK)^T X_K, then X_J -= L_KJ^T X_K for the rows above, with
 // the A operands read straight from the buffer.  W = alpha alpha^T - b b^T -
@@ -86,21 +86,18 @@ template <> struct WMma<double> {
 // lower-triangular tile (I, J), J <= I, in row-major packed order
 __host__ __device__ constexpr int tix(int I, int J) { return I * (I + 1) / 2 + J; }
 
-constexpr int kStageStride = 260;   // staged 16 x 16 tiles, padded so four tiles fall in different banks
+constexpr int kStageStride = 260;   // staged 16 x 16 tiles, padded so tiles four apart fall in different banks
 
 __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
   // su (3 P) for the whole kernel, then a work region: the panel (4 P) and sy,
   // sdk, swk (P each) during the factorisation; for the adjoint, one chunk of
-  // right-hand sides (P x (kWaveChunk + 1)) or four staged diagonal tiles
+  // right-hand sides (P x (kWaveChunk + 1)), which also holds the G staged
+  // diagonal tiles before the first chunk
   return 3 * 16 * G + (mode == 0 || mode == 2 ? 7 * 16 * G
-                                 : (16 * G * (kWaveChunk + 1) > 7 * 16 * G
-                                        ? (16 * G * (kWaveChunk + 1) > 4 * kStageStride ? 16 * G * (kWaveChunk + 1)
-                                                                                     : 4 * kStageStride)
-                                        : 7 * 16 * G));
+                                              : (16 * (kWaveChunk + 1) > kStageStride ? 16 * G * (kWaveChunk + 1)
+                                                                                      : G * kStageStride));
 }
 
-// Two waves per SIMD where the register file holds them without spilling
-// (FP32 up to G = 9, and the FP32 adjoint-only kernels); one otherwise.
 template <typename T, int G, int MODE>
 constexpr int wave_min_waves() { return sizeof(T) == 4 && (G <= 9 || MODE == 3) ? 2 : 1; }
 
@@ -181,13 +178,13 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
         T v = sig2 * mc.rho(x) + ((i == j) ? nug : T(0));
         if (!(i < p && j < p)) v = (i == j) ? T(1) : T(0);
-        acc[tix(I, J)][r] = v;
+        acc[tix(I, J)][r] = -v;   // the tiles hold the negated matrix (updates add L L^T)
       }
       if (I == (p >> 4)) {  // border row p: y_J
         const T yb = sy[j];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (I * 16 + M::row(lg, r) == p && j < p) acc[tix(I, J)][r] = yb;
+          if (I * 16 + M::row(lg, r) == p && j < p) acc[tix(I, J)][r] = -yb;
       }
       // D = 0 * 0 + C: hands the finished tile to the accumulator registers now,
       // so the generated values do not pile up in VGPRs until the first update
@@ -197,6 +194,78 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 
   // ---- factorisation, four columns per step -----------------------------------
   T* pan = work;  // pan[c * P + row], c < 4
+  // columns c0 .. c0 + 3 of tile column Kc to the panel
+  auto publish = [&](auto Kc_c, int c0) __attribute__((always_inline)) {
+    constexpr int Kc = decltype(Kc_c)::value;
+    if (lr >= c0 && lr < c0 + 4) {
+      static_for<Kc, G>(BV_CI(I) {
+        BV_CV(I);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pan[(lr - c0) * P + I * 16 + M::row(lg, r)] = acc[tix(I, Kc)][r];
+      });
+    }
+  };
+  // the panel at column k0: 4 x 4 diagonal block (same values in every lane),
+  // then its rows from the diagonal tile down (zero above the block, L_dd in
+  // it, TRSM below); pivots and border entries to LDS
+  auto factor_panel = [&](int k0) __attribute__((always_inline)) {
+    T Ld[4][4], rinv[4], piv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ld[r][c] = r >= c ? -pan[c * P + k0 + r] : T(0);   // panel holds -A
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const bool real = k0 + c < p;
+      T dsum = Ld[c][c];
+#pragma unroll
+      for (int j = 0; j < c; ++j) dsum -= Ld[c][j] * Ld[c][j];
+      piv[c] = real ? dsum : T(1);
+      const T ri = real ? M::rsqrt(dsum) : T(1);
+      rinv[c] = ri;
+      Ld[c][c] = real ? dsum * ri : T(1);
+#pragma unroll
+      for (int r = c + 1; r < 4; ++r) {
+        T v = Ld[r][c];
+#pragma unroll
+        for (int j = 0; j < c; ++j) v -= Ld[r][j] * Ld[c][j];
+        Ld[r][c] = real ? v * ri : T(0);
+      }
+    }
+    const int i0 = k0 & ~15;
+#pragma unroll
+    for (int q = 0; q < (P + 63) / 64; ++q) {
+      const int i = i0 + ln + 64 * q;
+      if (i < P) {
+        // branch-free: every lane runs the substitution, then rows above the
+        // block take zero and rows inside it take L_dd
+        const int di = i - k0;
+        T x[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          T v = -pan[c * P + i];
+#pragma unroll
+          for (int j = 0; j < c; ++j) v -= x[j] * Ld[c][j];
+          const T t = (k0 + c < p) ? v * rinv[c] : T(0);
+          T v2 = t;
+#pragma unroll
+          for (int rr = 0; rr < 4; ++rr) v2 = di == rr ? Ld[rr][c] : v2;
+          x[c] = di < 0 ? T(0) : v2;
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) pan[c * P + i] = x[c];
+        if (i == p) {
+#pragma unroll
+          for (int c = 0; c < 4; ++c) swk[k0 + c] = x[c];
+        }
+      }
+    }
+    if (ln == 0) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c) sdk[k0 + c] = piv[c];
+    }
+  };
+
   static_for<0, G>(BV_CI(K) {
     BV_CV(K);
     if (K * 16 >= p) return;
@@ -204,72 +273,10 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     for (int c0 = 0; c0 < 16; c0 += 4) {
       const int k0 = K * 16 + c0;
       if (k0 >= p) break;
-      if (lr >= c0 && lr < c0 + 4) {
-        static_for<K, G>(BV_CI(I) {
-          BV_CV(I);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) pan[(lr - c0) * P + I * 16 + M::row(lg, r)] = acc[tix(I, K)][r];
-        });
-      }
+      publish(std::integral_constant<int, K>{}, c0);
       __syncthreads();
-      // 4 x 4 diagonal block (same values in every lane)
-      T Ld[4][4], rinv[4], piv[4];
-#pragma unroll
-      for (int c = 0; c < 4; ++c)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) Ld[r][c] = r >= c ? pan[c * P + k0 + r] : T(0);
-#pragma unroll
-      for (int c = 0; c < 4; ++c) {
-        const bool real = k0 + c < p;
-        T dsum = Ld[c][c];
-#pragma unroll
-        for (int j = 0; j < c; ++j) dsum -= Ld[c][j] * Ld[c][j];
-        piv[c] = real ? dsum : T(1);
-        const T ri = real ? M::rsqrt(dsum) : T(1);
-        rinv[c] = ri;
-        Ld[c][c] = real ? dsum * ri : T(1);
-#pragma unroll
-        for (int r = c + 1; r < 4; ++r) {
-          T v = Ld[r][c];
-#pragma unroll
-          for (int j = 0; j < c; ++j) v -= Ld[r][j] * Ld[c][j];
-          Ld[r][c] = real ? v * ri : T(0);
-        }
-      }
-      // panel rows of tile K and below: zero above the block, L_dd in it, TRSM below
-#pragma unroll
-      for (int q = 0; q < (P - K * 16 + 63) / 64; ++q) {
-        const int i = K * 16 + ln + 64 * q;
-        if (i < P) {
-          // branch-free: every lane runs the substitution, then rows above the
-          // block take zero and rows inside it take L_dd
-          const int di = i - k0;
-          T x[4];
-#pragma unroll
-          for (int c = 0; c < 4; ++c) {
-            T v = pan[c * P + i];
-#pragma unroll
-            for (int j = 0; j < c; ++j) v -= x[j] * Ld[c][j];
-            const T t = (k0 + c < p) ? v * rinv[c] : T(0);
-            T v2 = t;
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) v2 = di == rr ? Ld[rr][c] : v2;
-            x[c] = di < 0 ? T(0) : v2;
-          }
-#pragma unroll
-          for (int c = 0; c < 4; ++c) pan[c * P + i] = x[c];
-          if (i == p) {
-#pragma unroll
-            for (int c = 0; c < 4; ++c) swk[k0 + c] = x[c];
-          }
-        }
-      }
-      if (ln == 0) {
-#pragma unroll
-        for (int c = 0; c < 4; ++c) sdk[k0 + c] = piv[c];
-      }
+      factor_panel(k0);
       __syncthreads();
-      // rank-4 update of the trailing tiles: D -= L_I L_J^T
       T v[G];
       static_for<K, G>(BV_CI(I) {
         BV_CV(I);
@@ -277,10 +284,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       });
       static_for<K, G>(BV_CI(I) {
         BV_CV(I);
-        const T nv = -v[I];
         static_for<K, I + 1>(BV_CI(J) {
           BV_CV(J);
-          acc[tix(I, J)] = M::op(nv, v[J], acc[tix(I, J)]);
+          acc[tix(I, J)] = M::op(v[I], v[J], acc[tix(I, J)]);
         });
       });
       if (MODE != 0 && lr >= c0 && lr < c0 + 4) {
@@ -351,42 +357,50 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     wreg[k] = j < p ? Lg[(Ip * (Ip + 1) / 2 + (j >> 4)) * 256 + M::at(rp, j & 15)] : T(0);
   }
 
-  // ---- inverses of the diagonal 16 x 16 blocks of L, four at a time ----------
-  // lane (c = l % 16, g = l / 16) forms column c of inv(L_KK), K = K0 + g, by
-  // forward substitution; the border row and the padding are identity rows
-  for (int K0 = 0; K0 < Gp; K0 += 4) {
-    __syncthreads();
+  // ---- inverses of the diagonal 16 x 16 blocks of L ---------------------------
+  // all Gp blocks staged at once (the border row and the padding become
+  // identity rows); lane (c = l % 16, g = l / 16) forms column c of inv(L_KK)
+  // for K = g, g + 4, g + 8 by forward substitution, three independent chains
+  {
+    constexpr int NB = (G + 3) / 4;   // blocks per lane group
+    for (int K = 0; K < Gp; ++K) {
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-      const int K = K0 + g;
-      if (K < Gp) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int rw = M::row(lg, r);
-          const int i = K * 16 + rw, j = K * 16 + lr;
-          T v = Lg[(K * (K + 1) / 2 + K) * 256 + ln * 4 + r];
-          if (i >= p || j >= p) v = (i == j) ? T(1) : T(0);
-          X[g * kStageStride + rw * 16 + lr] = v;
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int rw = M::row(lg, r);
+        const int i = K * 16 + rw, j = K * 16 + lr;
+        T v = Lg[(K * (K + 1) / 2 + K) * 256 + ln * 4 + r];
+        if (i >= p || j >= p) v = (i == j) ? T(1) : T(0);
+        X[K * kStageStride + rw * 16 + lr] = v;
       }
     }
     __syncthreads();
-    const int K = K0 + lg;
-    if (K < Gp) {
-      const T* Lk = X + lg * kStageStride;
-      const int c = lr;
-      T x[16];
+    const int c = lr;
+    T x[NB][16];
+    const T* Lk[NB];
 #pragma unroll
-      for (int i = 0; i < 16; ++i) {
+    for (int jb = 0; jb < NB; ++jb) {
+      const int K = lg + 4 * jb;
+      Lk[jb] = X + (K < Gp ? K : 0) * kStageStride;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+#pragma unroll
+      for (int jb = 0; jb < NB; ++jb) {
         T sum = T(0);
 #pragma unroll
-        for (int k = 0; k < i; ++k) sum += Lk[i * 16 + k] * x[k];
-        const T rd = T(1) / Lk[i * 16 + i];
-        x[i] = i < c ? T(0) : (i == c ? rd : -sum * rd);
+        for (int k = 0; k < i; ++k) sum += Lk[jb][i * 16 + k] * x[jb][k];
+        const T rd = T(1) / Lk[jb][i * 16 + i];
+        x[jb][i] = i < c ? T(0) : (i == c ? rd : -sum * rd);
       }
-      T* dst = Lg + (K * (K + 1) / 2 + K) * 256;
+    }
 #pragma unroll
-      for (int i = 0; i < 16; ++i) dst[M::at(i, c)] = x[i];
+    for (int jb = 0; jb < NB; ++jb) {
+      const int K = lg + 4 * jb;
+      if (K < Gp) {
+        T* dst = Lg + (K * (K + 1) / 2 + K) * 256;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) dst[M::at(i, c)] = x[jb][i];
+      }
     }
   }
   __syncthreads();
@@ -570,6 +584,19 @@ static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, i
     if (g == 10) return launch_wave_g<T, 10, MODE>(a, thp, grid, s);
     if (g == 11) return launch_wave_g<T, 11, MODE>(a, thp, grid, s);
     return hipErrorInvalidValue;
+  } else if constexpr (MODE == 1 && sizeof(T) == 4) {   // FP32 G >= 10 use the split gradient
+    switch (g) {
+      case 1: return launch_wave_g<T, 1, MODE>(a, thp, grid, s);
+      case 2: return launch_wave_g<T, 2, MODE>(a, thp, grid, s);
+      case 3: return launch_wave_g<T, 3, MODE>(a, thp, grid, s);
+      case 4: return launch_wave_g<T, 4, MODE>(a, thp, grid, s);
+      case 5: return launch_wave_g<T, 5, MODE>(a, thp, grid, s);
+      case 6: return launch_wave_g<T, 6, MODE>(a, thp, grid, s);
+      case 7: return launch_wave_g<T, 7, MODE>(a, thp, grid, s);
+      case 8: return launch_wave_g<T, 8, MODE>(a, thp, grid, s);
+      case 9: return launch_wave_g<T, 9, MODE>(a, thp, grid, s);
+      default: return hipErrorInvalidValue;
+    }
   } else {
   switch (g) {
     case 1: return launch_wave_g<T, 1, MODE>(a, thp, grid, s);

@@ -67,4 +67,4 @@ def test_fp32_wave_kernels_keep_their_tiles_in_registers():
         assert r["scratch"] == 0, (name, r)
         if g <= 9:
             assert r["occupancy"] >= 2, (name, r)
-    assert seen == 26   # G = 1..11 value and gradient, G = 10, 11 split gradient
+    assert seen == 24   # value G = 1..11, fused gradient G = 1..9, split gradient G = 10, 11 (two kernels)
