@@ -16,4 +16,6 @@ Contents (each function cites the passage of the paper it follows):
                 blocks (csrc/bv_oracle.c), for the larger workloads
   simulate    - exact-GP and sequential-Vecchia data simulators
   learned     - binned empirical variogram and an FP64 MLP forward/backward
+  predict     - block Vecchia prediction (Alg. 2) and univariate conditional
+                simulation with PICP / MSPE
 """
