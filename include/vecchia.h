@@ -185,6 +185,7 @@ typedef struct {
   int32_t lds_bytes;                          /* device LDS limit per workgroup */
   int32_t bucket_main;                        /* class with the most blocks */
   void* exec;      /* side streams and events of concurrent size classes (vecchia_plan_destroy) */
+  int32_t kind;    /* 0 likelihood plan, 1 prediction plan (VECCHIA_PLAN_PREDICT) */
 } vecchia_plan;
 
 size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
@@ -193,6 +194,12 @@ size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
  * R = 16 and holds the bordered matrix, p + 1 <= 16 G).  VECCHIA_EINVAL for an
  * unknown configuration. */
 int vecchia_tile_config(int32_t engine, int32_t cfg, int32_t* R, int32_t* G);
+/* engine may carry VECCHIA_PLAN_PREDICT (with VECCHIA_ENGINE_MFMA and
+ * max_theta = 1): a plan for vecchia_predict over blocks of new locations,
+ * sized by pred_rows(m_i) + l_i where pred_rows rounds m_i up to a multiple
+ * of 4 (every block must fit VECCHIA_MAX_JOINT, else VECCHIA_EUNSUPPORTED).
+ * The likelihood entry points reject prediction plans. */
+#define VECCHIA_PLAN_PREDICT 16
 int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, const int32_t* nbr_ptr,
                       int64_t n, int64_t bc, int32_t max_theta, int32_t engine,
                       void* workspace, size_t ws_bytes, void* stream);
@@ -252,6 +259,63 @@ int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const
                         const vecchia_theta* theta, int32_t ntheta, int32_t precision,
                         double* loglik, double* grad, int32_t* counters, double* partial, double* gpartial,
                         void* stream);
+
+/* ------------------------------------------------------------ prediction --
+ * Block Vecchia prediction (Section 2.4, Alg. 2).  The n_new new locations
+ * are grouped into blocks B*_1..B*_bc (for instance vecchia_blocks on them,
+ * then vecchia_permute into block order), and each block conditions on the m
+ * observations nearest its centroid.
+ *
+ * vecchia_pred_neighbors: as vecchia_neighbors (same centroid, distance and
+ * tie rule), but every observation is a candidate of every block:
+ * m_i = min(m, n_obs); m = -1 selects all observations (exact kriging).
+ *   locs_obs   n_obs x d observed locations
+ *   locs_new   n_new x d new locations in block order
+ *   block_ptr  bc+1 int32 offsets into locs_new (block_ptr[bc] = n_new)
+ *   nbr_ptr    out, bc+1 int32;  nbr_idx: out, indices into locs_obs
+ *   workspace  >= vecchia_pred_neighbors_workspace_size(n_obs, n_new, bc, d, m)
+ * Synchronises `stream`. */
+size_t vecchia_pred_neighbors_workspace_size(int64_t n_obs, int64_t n_new, int64_t bc, int32_t d, int32_t m);
+int vecchia_pred_neighbors(const double* locs_obs, int64_t n_obs, const double* locs_new, int64_t n_new,
+                           int32_t d, const double* metric_scale, const int32_t* block_ptr, int64_t bc, int32_t m,
+                           int32_t* nbr_ptr, int32_t* nbr_idx, int64_t nbr_cap,
+                           void* workspace, size_t ws_bytes, void* stream);
+
+/* vecchia_predict: per block, in FP64, the conditional mean and covariance of
+ * the new values given the neighbours' observations,
+ *   mu_B = K(B,N) K(N,N)^-1 y_N,   Sigma_B = K(B,B) - K(B,N) K(N,N)^-1 K(N,B),
+ * with the nugget on the diagonal of K(N,N) and K(B,B) (new noisy
+ * observations) and never in K(B,N).  One wave per block eliminates only the
+ * neighbour columns of the bordered joint matrix [[K(N,N), .], [K(B,N),
+ * K(B,B)], [y_N^T, 0]]; the remaining Schur complement holds Sigma_B and -mu_B.
+ *   plan       vecchia_plan_init(block_ptr, nbr_ptr, n_new, bc, 1,
+ *              VECCHIA_ENGINE_MFMA | VECCHIA_PLAN_PREDICT, ...)
+ *   y_obs      n_obs observed values
+ *   theta      host, one parameter vector
+ *   mean, var  out, n_new doubles each, in the block order of locs_new
+ *   cov        out or NULL: bc * ldc * ldc doubles; block i's l_i x l_i
+ *              covariance, row-major, at cov + i * ldc * ldc (ldc >= plan->lmax)
+ * A block whose neighbour covariance is not positive definite gets NaN
+ * outputs. */
+int vecchia_predict(const vecchia_plan* plan, const double* locs_obs, const double* y_obs,
+                    const double* locs_new, int32_t d, const int32_t* block_ptr, const int32_t* nbr_ptr,
+                    const int32_t* nbr_idx, const vecchia_theta* theta, double* mean, double* var,
+                    double* cov, int32_t ldc, void* stream);
+
+/* vecchia_condsim: univariate conditional simulation (Section 2.4): R draws
+ * mean_j + sqrt(var_j) z_rj per location; their sample mean and standard
+ * deviation (divisor R - 1), the interval mean -/+ 1.959964 sd, and, when
+ * y_true is given, stats = (PICP, MSPE): the fraction of true values inside
+ * their interval and the mean squared difference between sample mean and
+ * truth (Section 3).  The random numbers are inputs.
+ *   z          R x n doubles, draw r of location j at z[r * n + j]; R >= 2
+ *   smean, ssd, lo, hi   out or NULL, n doubles each
+ *   stats      out, 2 doubles (required with y_true)
+ *   workspace  >= vecchia_condsim_workspace_size(n) bytes */
+size_t vecchia_condsim_workspace_size(int64_t n);
+int vecchia_condsim(const double* mean, const double* var, int64_t n, const double* z, int32_t R,
+                    const double* y_true, double* smean, double* ssd, double* lo, double* hi, double* stats,
+                    void* workspace, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------- simulate --
  * Sequential Vecchia simulator (data generator of the synthetic workloads):

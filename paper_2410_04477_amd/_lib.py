@@ -12,6 +12,7 @@ LIB_PATH = os.path.join(_PKG, "libvecchia.so")
 MAX_BUCKETS = 24
 MAX_JOINT = 175
 ENGINE_MFMA, ENGINE_TILES, ENGINE_MFMA_WG = 0, 1, 2
+PLAN_PREDICT = 16
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, FP32_BULK = 0, 1
@@ -35,7 +36,7 @@ class Plan(ctypes.Structure):
                 ("nlarge", ctypes.c_int64), ("large_slots", ctypes.c_int32), ("large_slot_elems", ctypes.c_int64),
                 ("aux_ws_bytes", ctypes.c_size_t), ("aux_ws", ctypes.c_void_p),
                 ("bucket_lmax", ctypes.c_int32 * MAX_BUCKETS), ("lds_bytes", ctypes.c_int32),
-                ("bucket_main", ctypes.c_int32), ("exec", ctypes.c_void_p)]
+                ("bucket_main", ctypes.c_int32), ("exec", ctypes.c_void_p), ("kind", ctypes.c_int32)]
 
 
 class VecchiaError(RuntimeError):
@@ -71,6 +72,11 @@ SIGNATURES = {
     "vecchia_plan_destroy": (ctypes.c_int, [P]),
     "vecchia_plan_set_timing": (ctypes.c_int, [P, ctypes.c_int]),
     "vecchia_plan_timing": (ctypes.c_int, [P, P, P, ctypes.c_int]),
+    "vecchia_pred_neighbors_workspace_size": (SZ, [I64, I64, I64, I32, I32]),
+    "vecchia_pred_neighbors": (ctypes.c_int, [P, I64, P, I64, I32, P, P, I64, I32, P, P, I64, P, SZ, P]),
+    "vecchia_predict": (ctypes.c_int, [P, P, P, P, I32, P, P, P, P, P, P, P, I32, P]),
+    "vecchia_condsim_workspace_size": (SZ, [I64]),
+    "vecchia_condsim": (ctypes.c_int, [P, P, I64, P, I32, P, P, P, P, P, P, P, SZ, P]),
 }
 
 _lib = None

@@ -112,7 +112,7 @@ class Plan:
     """Launch schedule for one block / neighbour structure (vecchia_plan_init)."""
 
     def __init__(self, block_ptr: torch.Tensor, nbr_ptr: torch.Tensor, n: int, max_theta: int = 1,
-                 engine: str = "mfma"):
+                 engine: str = "mfma", predict: bool = False):
         _dev_check(block_ptr, nbr_ptr)
         if block_ptr.dtype != torch.int32 or nbr_ptr.dtype != torch.int32:
             raise ValueError("block_ptr / nbr_ptr must be int32")
@@ -121,8 +121,9 @@ class Plan:
         self.ws = torch.empty(int(lib.vecchia_plan_workspace_size(bc, max_theta)), dtype=torch.uint8,
                               device=block_ptr.device)
         self.c = L.Plan()
+        flags = ENGINES[engine] | (L.PLAN_PREDICT if predict else 0)
         L.check(lib.vecchia_plan_init(ctypes.byref(self.c), _p(block_ptr), _p(nbr_ptr), n, bc, max_theta,
-                                      ENGINES[engine], _p(self.ws), self.ws.numel(), _stream(block_ptr.device)),
+                                      flags, _p(self.ws), self.ws.numel(), _stream(block_ptr.device)),
                 "vecchia_plan_init")
         self.engine = engine
         self.aux_ws = None
@@ -133,9 +134,9 @@ class Plan:
         self.block_ptr, self.nbr_ptr = block_ptr, nbr_ptr
 
     def __del__(self):
-        # side streams and events of the concurrent size classes
+        # timing records, side streams and events of the concurrent size classes
         try:
-            if getattr(self, "c", None) is not None and self.c.exec:
+            if getattr(self, "c", None) is not None and (self.c.exec or self.c.timing):
                 L.lib().vecchia_plan_destroy(ctypes.byref(self.c))
         except Exception:
             pass
@@ -168,13 +169,6 @@ class Plan:
         """Block ids grouped by size class (device int32 view into the plan workspace)."""
         off = int(self.c.off_sched)
         return self.ws[off: off + 4 * self.bc].view(torch.int32)
-
-    def __del__(self):
-        try:
-            if self.c.timing:
-                L.lib().vecchia_plan_set_timing(ctypes.byref(self.c), 0)
-        except Exception:
-            pass
 
     def buckets(self):
         return [(int(self.c.bucket_cfg[q]), int(self.c.bucket_off[q + 1] - self.c.bucket_off[q]))
@@ -296,3 +290,68 @@ def adam(param: torch.Tensor, grad: torch.Tensor, m: torch.Tensor, v: torch.Tens
     _dev_check(param, grad, m, v)
     L.check(L.lib().vecchia_adam(_p(param), _p(grad), _p(m), _p(v), param.numel(), lr, beta1, beta2, eps, step,
                                  _stream(param.device)), "vecchia_adam")
+
+
+# ---------------------------------------------------------------- prediction
+
+
+def pred_neighbors(locs_obs: torch.Tensor, locs_new: torch.Tensor, block_ptr: torch.Tensor, m: int,
+                   metric_scale: Optional[Sequence[float]] = None):
+    """The m observations nearest each prediction block's centroid (every
+    observation is a candidate).  Returns (nbr_ptr int32, nbr_idx int32 into locs_obs)."""
+    _dev_check(locs_obs, locs_new, block_ptr)
+    n_obs, d = locs_obs.shape
+    n_new = locs_new.shape[0]
+    bc = block_ptr.numel() - 1
+    lib = L.lib()
+    cap = max(1, min(bc * (n_obs if m < 0 else min(m, n_obs)), 2**31 - 1))
+    ws = torch.empty(int(lib.vecchia_pred_neighbors_workspace_size(n_obs, n_new, bc, d, m)), dtype=torch.uint8,
+                     device=locs_obs.device)
+    nptr = torch.empty(bc + 1, dtype=torch.int32, device=locs_obs.device)
+    nidx = torch.empty(cap, dtype=torch.int32, device=locs_obs.device)
+    ms = (ctypes.c_double * d)(*metric_scale) if metric_scale is not None else None
+    L.check(lib.vecchia_pred_neighbors(_p(locs_obs), n_obs, _p(locs_new), n_new, d, ms, _p(block_ptr), bc, m,
+                                       _p(nptr), _p(nidx), cap, _p(ws), ws.numel(), _stream(locs_obs.device)),
+            "vecchia_pred_neighbors")
+    total = int(nptr[-1].item())
+    return nptr, nidx[:total].clone()
+
+
+def predict(plan: Plan, locs_obs: torch.Tensor, y_obs: torch.Tensor, locs_new: torch.Tensor,
+            nbr_idx: torch.Tensor, theta, want_cov: bool = False):
+    """Block Vecchia prediction (vecchia_predict) with a plan built with
+    predict=True.  Returns (mean[n_new], var[n_new], cov[bc, ldc, ldc] or None)."""
+    _dev_check(locs_obs, y_obs, locs_new, nbr_idx)
+    dev = locs_new.device
+    n_new, d = locs_new.shape
+    th = make_theta(theta)
+    mean = torch.empty(n_new, dtype=torch.float64, device=dev)
+    var = torch.empty(n_new, dtype=torch.float64, device=dev)
+    ldc = max(1, int(plan.c.lmax))
+    cov = torch.empty((plan.bc, ldc, ldc), dtype=torch.float64, device=dev) if want_cov else None
+    L.check(L.lib().vecchia_predict(ctypes.byref(plan.c), _p(locs_obs), _p(y_obs), _p(locs_new), d,
+                                    _p(plan.block_ptr), _p(plan.nbr_ptr), _p(nbr_idx), ctypes.byref(th), _p(mean),
+                                    _p(var), _p(cov), ldc, _stream(dev)), "vecchia_predict")
+    return mean, var, cov
+
+
+def condsim(mean: torch.Tensor, var: torch.Tensor, z: torch.Tensor, y_true: Optional[torch.Tensor] = None):
+    """Univariate conditional simulation (vecchia_condsim); z is R x n.
+    Returns dict of sample_mean, sample_sd, lo, hi and, with y_true, picp and mspe."""
+    _dev_check(mean, var, z, y_true)
+    n = mean.numel()
+    r = z.shape[0]
+    if z.shape != (r, n):
+        raise ValueError("z must be R x n")
+    dev = mean.device
+    lib = L.lib()
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("sample_mean", "sample_sd", "lo", "hi")}
+    stats = torch.empty(2, dtype=torch.float64, device=dev)
+    ws = torch.empty(int(lib.vecchia_condsim_workspace_size(n)), dtype=torch.uint8, device=dev)
+    L.check(lib.vecchia_condsim(_p(mean), _p(var), n, _p(z), r, _p(y_true), _p(out["sample_mean"]),
+                                _p(out["sample_sd"]), _p(out["lo"]), _p(out["hi"]), _p(stats), _p(ws), ws.numel(),
+                                _stream(dev)), "vecchia_condsim")
+    if y_true is not None:
+        st = stats.cpu()
+        out["picp"], out["mspe"] = float(st[0]), float(st[1])
+    return out

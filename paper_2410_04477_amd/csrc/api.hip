@@ -114,7 +114,10 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   if (!plan || !block_ptr || !nbr_ptr || !workspace || n <= 0 || bc <= 0 || bc > n || max_theta <= 0 ||
       n >= (int64_t)1 << 31 || (int64_t)bc * max_theta >= (int64_t)1 << 31)
     return VECCHIA_EINVAL;
+  const bool predict = (engine & VECCHIA_PLAN_PREDICT) != 0;
+  engine &= ~VECCHIA_PLAN_PREDICT;
   if (engine != kEngineMfma && engine != kEngineTiles && engine != kEngineMfmaWg) return VECCHIA_EINVAL;
+  if (predict && (engine != kEngineMfma || max_theta != 1)) return VECCHIA_EINVAL;
   const PlanLayout L = plan_layout(bc, max_theta);
   if (ws_bytes < L.total) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
@@ -128,7 +131,8 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   VCHECK_HIP(launch_fill_int(maxes, 16, 0, s));
   VCHECK_HIP(launch_fill_int(lmax_cfg, 32, 0, s));
   VCHECK_HIP(launch_fill_int(reinterpret_cast<int*>(stats), 16, 0, s));
-  VCHECK_HIP(launch_classify(block_ptr, nbr_ptr, (int)bc, cfg_of, counts, stats, maxes, lmax_cfg, engine, s));
+  VCHECK_HIP(launch_classify(block_ptr, nbr_ptr, (int)bc, cfg_of, counts, stats, maxes, lmax_cfg, engine,
+                             predict ? 4 : 1, s));
   int hcounts[32];
   int hmax[4];
   int hlmax[32];
@@ -142,6 +146,8 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
     // a block with no points, or larger than even the global-workspace kernel takes
     return hmax[0] > 16383 ? VECCHIA_EUNSUPPORTED : VECCHIA_EINVAL;
   }
+  // prediction has no large-block path: every block must fit the one-wave kernel
+  if (predict && hcounts[kLargeCfg] > 0) return VECCHIA_EUNSUPPORTED;
   const int ncfg = engine == kEngineTiles ? kNumCfgs : kMfmaMaxG;
   // merge sparse size classes upward: a class's kernel also takes every smaller
   // block, and a launch of a few blocks costs a whole block's latency
@@ -191,7 +197,7 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
     plan->large_slot_elems = P * P;
     plan->aux_ws_bytes = (size_t)plan->large_slots * (size_t)(P * P) * sizeof(double);
   }
-  if (engine == kEngineMfma) {
+  if (engine == kEngineMfma && !predict) {
     // adjoint factor tiles: every work item of the largest class, FP64, capped
     size_t need = 0;
     for (int c = 0; c < kMfmaMaxG; ++c)
@@ -227,6 +233,7 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   plan->off_chunk = L.chunk;
   plan->off_grad = L.grad;
   plan->engine = engine;
+  plan->kind = predict ? 1 : 0;
   int dev = 0, lds = 0;
   VCHECK_HIP(hipGetDevice(&dev));
   VCHECK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
@@ -467,6 +474,7 @@ static int check_common(const vecchia_plan* plan, const double* locs, const doub
                         const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
                         const vecchia_theta* theta, int32_t ntheta, int32_t precision) {
   if (!plan || !plan->ws || !locs || !y || !block_ptr || !nbr_ptr || !nbr_idx || !theta) return VECCHIA_EINVAL;
+  if (plan->kind != 0) return VECCHIA_EINVAL;   // a prediction plan
   if (d < 1 || d > 3 || ntheta < 1 || ntheta > plan->max_theta) return VECCHIA_EINVAL;
   if (precision != VECCHIA_FP64 && precision != VECCHIA_FP32_BULK && precision != VECCHIA_FP32_BULK_FORCE_REFACTOR)
     return VECCHIA_EINVAL;
@@ -681,5 +689,55 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
       VCHECK_HIP(hipMemcpyAsync(gpartial + (size_t)t0 * bc * 3, gpart, sizeof(double) * (size_t)nt * bc * 3,
                                 hipMemcpyDeviceToDevice, s));
   }
+  return VECCHIA_OK;
+}
+
+// ------------------------------------------------------------- predict ----
+
+extern "C" int vecchia_predict(const vecchia_plan* plan, const double* locs_obs, const double* y_obs,
+                               const double* locs_new, int32_t d, const int32_t* block_ptr, const int32_t* nbr_ptr,
+                               const int32_t* nbr_idx, const vecchia_theta* theta, double* mean, double* var,
+                               double* cov, int32_t ldc, void* stream) {
+  if (!plan || plan->kind != 1 || !plan->ws || !locs_obs || !y_obs || !locs_new || !block_ptr || !nbr_ptr ||
+      !nbr_idx || !theta || !mean || !var)
+    return VECCHIA_EINVAL;
+  if (d < 1 || d > 3 || (cov && ldc < plan->lmax)) return VECCHIA_EINVAL;
+  ThetaPack thp;
+  memset(&thp, 0, sizeof(thp));
+  if (!theta_to_dev(*theta, d, thp.t[0]))
+    return (theta->nu == 0.5 || theta->nu == 1.5 || theta->nu == 2.5) ? VECCHIA_EINVAL : VECCHIA_EUNSUPPORTED;
+  hipStream_t s = (hipStream_t)stream;
+  AdjArgs a;
+  memset(&a, 0, sizeof(a));
+  a.locs = locs_obs;
+  a.y = y_obs;
+  a.block_ptr = block_ptr;
+  a.nbr_ptr = nbr_ptr;
+  a.nbr_idx = nbr_idx;
+  a.ntheta = 1;
+  a.bc = (int)plan->bc;
+  a.d = d;
+  a.locs2 = locs_new;
+  a.out_mean = mean;
+  a.out_var = var;
+  a.out_cov = cov;
+  a.ldc = cov ? ldc : 0;
+  const int* sched = at<int>(plan->ws, plan->off_sched);
+  const bool conc = plan->exec != nullptr;
+  TimingRec span;
+  VCHECK_HIP(time_begin(plan, plan->nbuckets, s, span));
+  if (conc) VCHECK_HIP(fork_streams(plan, s));
+  for (int q = plan->nbuckets - 1; q >= 0; --q) {
+    const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
+    const hipStream_t sq = class_stream(plan, q, s, conc);
+    a.sched = sched + plan->bucket_off[q];
+    a.nsched = ns;
+    TimingRec tr;
+    VCHECK_HIP(time_begin(plan, q, sq, tr));
+    VCHECK_HIP(launch_wave(plan->bucket_cfg[q] + 1, false, 4, a, thp, ns, sq));
+    VCHECK_HIP(time_end(plan, sq, tr));
+  }
+  if (conc) VCHECK_HIP(join_streams(plan, s));
+  VCHECK_HIP(time_end(plan, s, span));
   return VECCHIA_OK;
 }

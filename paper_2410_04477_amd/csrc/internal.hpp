@@ -50,6 +50,13 @@ struct AdjArgs {
   int64_t coef_stride;   // coefficient mode: entries per theta (nbr_ptr[bc])
   void* tiles;           // one-wave adjoint: factor tiles, one slot per work item of the launch
   int item_base;         // first work item of the launch (launches in chunks of the tile buffer)
+  // prediction (one-wave mode 4): block rows come from locs2 (new locations in
+  // block order), neighbour rows from locs / y (observations)
+  const double* locs2;
+  double* out_mean;      // [new location]: conditional mean
+  double* out_var;       // [new location]: conditional variance
+  double* out_cov;       // [block][ldc][ldc]: conditional covariance, or null
+  int ldc;
 };
 
 hipError_t launch_adjoint(int cfg, bool fp32, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
@@ -70,6 +77,8 @@ constexpr size_t kAdjTileCap = (size_t)4 << 30;
 bool wave_fits(int g, bool fp32);
 // gradient as two launches (factor + tiles, then the adjoint from the tiles)
 inline bool wave_split(int g, bool fp32) { return fp32 && g >= 10; }
+// prediction: round the conditioning-set size up to the factorisation's panel width
+__host__ __device__ constexpr int pred_rows(int m) { return (m + 3) & ~3; }
 hipError_t launch_wave_f32(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 hipError_t launch_wave_f64(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 hipError_t launch_wave(int g, bool fp32, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
@@ -99,8 +108,11 @@ hipError_t launch_large(bool fp32, const LargeArgs& a, const ThetaPack& thp, int
 // leading dimension of the LDS right-hand sides for l_max (matrix-core engine)
 inline int mfma_ldx(int nr_max) { return 16 * ((nr_max + 15) / 16) + 1; }
 
+// mpad: conditioning-set sizes are rounded up to a multiple of mpad (4 for
+// prediction plans, whose neighbour rows end on a panel boundary)
 hipError_t launch_classify(const int* block_ptr, const int* nbr_ptr, int bc, int* cfg_of, int* counts,
-                           unsigned long long* stats, int* maxes, int* lmax_cfg, int engine, hipStream_t s);
+                           unsigned long long* stats, int* maxes, int* lmax_cfg, int engine, int mpad,
+                           hipStream_t s);
 hipError_t launch_scatter(const int* cfg_of, int bc, const int* cfg_off, int* cursor, int* sched, hipStream_t s);
 hipError_t launch_remap(int* cfg_of, int bc, const int* remap, hipStream_t s);
 // size classes with fewer blocks than this run with the next larger populated class

@@ -276,6 +276,7 @@ struct KnnArgs {
   const int* cell_pts;
   int* status;          // set to 1 if a block could not be resolved within capacity
   int brute_first;      // blocks [0, brute_first) use the exhaustive path (set by host ordering)
+  int nref;             // candidates are the points below min(block start, nref)
 };
 
 // squared distance with a fixed evaluation order and no fused multiply-add
@@ -375,7 +376,7 @@ __global__ void __launch_bounds__(KNN_T) knn_kernel(KnnArgs a, int bc) {
   __shared__ double scen[3];
   const int b = blockIdx.x;
   if (b >= bc) return;
-  const int limit = a.block_ptr[b];
+  const int limit = min(a.block_ptr[b], a.nref);
   const int out0 = a.nbr_ptr[b];
   const int mi = a.nbr_ptr[b + 1] - out0;
   if (mi == 0) return;
@@ -722,28 +723,20 @@ extern "C" size_t vecchia_neighbors_workspace_size(int64_t n, int64_t bc, int32_
   return nbr_layout(n, max_cells(n)).total;
 }
 
-extern "C" int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const double* metric_scale,
-                                 const int32_t* block_ptr, int64_t bc, int32_t m, int32_t* nbr_ptr, int32_t* nbr_idx,
-                                 int64_t nbr_cap, void* workspace, size_t ws_bytes, void* stream) {
-  if (!locs_perm || !block_ptr || !nbr_ptr || !nbr_idx || !workspace) return VECCHIA_EINVAL;
-  if (n <= 0 || bc <= 0 || d < 1 || d > 3 || m < -1 || n >= ((int64_t)1 << 31)) return VECCHIA_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  double w[3] = {1.0, 1.0, 1.0};
-  for (int k = 0; k < d; ++k) {
-    w[k] = metric_scale ? metric_scale[k] : 1.0;
-    if (!(w[k] > 0) || !isfinite(w[k])) return VECCHIA_EINVAL;
-  }
-  // conditioning-set sizes m_i = min(m, points before block i)
-  std::vector<int> hb(bc + 1);
-  PCHECK(hipMemcpyAsync(hb.data(), block_ptr, sizeof(int) * (bc + 1), hipMemcpyDeviceToHost, s));
-  PCHECK(hipStreamSynchronize(s));
-  if (hb[0] != 0 || hb[bc] > n) return VECCHIA_EINVAL;
+// Neighbour search over the points of `locs` (n x d) for the blocks of
+// block_ptr (device; hb is its host copy): candidates of block i are the
+// points below min(hb[i], nref).
+static int neighbors_impl(const double* locs, int64_t n, int32_t d, const double* w, const int32_t* block_ptr,
+                          const std::vector<int>& hb, int64_t bc, int32_t m, int nref, int32_t* nbr_ptr,
+                          int32_t* nbr_idx, int64_t nbr_cap, void* workspace, size_t ws_bytes, hipStream_t s) {
+  // conditioning-set sizes m_i = min(m, candidates of block i)
   std::vector<int> hn(bc + 1);
   int64_t tot = 0;
   hn[0] = 0;
   for (int64_t i = 0; i < bc; ++i) {
     if (hb[i + 1] <= hb[i]) return VECCHIA_EINVAL;
-    const int64_t mi = m < 0 ? hb[i] : std::min<int64_t>(m, hb[i]);
+    const int64_t lim = std::min<int64_t>(hb[i], nref);
+    const int64_t mi = m < 0 ? lim : std::min<int64_t>(m, lim);
     tot += mi;
     if (tot >= ((int64_t)1 << 31)) return VECCHIA_ENOMEM;
     hn[i + 1] = (int)tot;
@@ -760,7 +753,7 @@ extern "C" int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, 
   NbrLayout L0 = nbr_layout(n, 1);
   if (ws_bytes < L0.total) return VECCHIA_ENOMEM;
   double lo[3], hi[3];
-  int st = bbox(locs_perm, n, d, w, at<double>(workspace, L0.part), lo, hi, s);
+  int st = bbox(locs, n, d, w, at<double>(workspace, L0.part), lo, hi, s);
   if (st) return st;
   double vol = 1.0;
   double extk[3];
@@ -796,7 +789,7 @@ extern "C" int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, 
   int* key2 = at<int>(workspace, L.key2);
   int* cell_pts = at<int>(workspace, L.val2);
   int* cstart = at<int>(workspace, L.cstart);
-  hipLaunchKernelGGL(cell_key_kernel, dim3(cdiv64(n, 256)), dim3(256), 0, s, locs_perm, n, d, w[0], w[1], w[2], g, key,
+  hipLaunchKernelGGL(cell_key_kernel, dim3(cdiv64(n, 256)), dim3(256), 0, s, locs, n, d, w[0], w[1], w[2], g, key,
                      val);
   PCHECK(hipGetLastError());
   int nbits = 1;
@@ -810,7 +803,7 @@ extern "C" int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, 
   hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, status, 8, 0);
   KnnArgs a;
   memset(&a, 0, sizeof(a));
-  a.locs = locs_perm;
+  a.locs = locs;
   a.d = d;
   for (int k = 0; k < 3; ++k) a.w[k] = w[k];
   a.block_ptr = block_ptr;
@@ -821,10 +814,90 @@ extern "C" int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, 
   a.cell_start = cstart;
   a.cell_pts = cell_pts;
   a.status = status;
+  a.nref = nref;
   hipLaunchKernelGGL(knn_kernel, dim3((unsigned)bc), dim3(KNN_T), 0, s, a, (int)bc);
   PCHECK(hipGetLastError());
   int hs = 0;
   PCHECK(hipMemcpyAsync(&hs, status, sizeof(int), hipMemcpyDeviceToHost, s));
   PCHECK(hipStreamSynchronize(s));
   return hs ? VECCHIA_EUNSUPPORTED : VECCHIA_OK;
+}
+
+static int metric_weights(const double* metric_scale, int d, double* w) {
+  for (int k = 0; k < 3; ++k) w[k] = 1.0;
+  for (int k = 0; k < d; ++k) {
+    w[k] = metric_scale ? metric_scale[k] : 1.0;
+    if (!(w[k] > 0) || !isfinite(w[k])) return VECCHIA_EINVAL;
+  }
+  return VECCHIA_OK;
+}
+
+extern "C" int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const double* metric_scale,
+                                 const int32_t* block_ptr, int64_t bc, int32_t m, int32_t* nbr_ptr, int32_t* nbr_idx,
+                                 int64_t nbr_cap, void* workspace, size_t ws_bytes, void* stream) {
+  if (!locs_perm || !block_ptr || !nbr_ptr || !nbr_idx || !workspace) return VECCHIA_EINVAL;
+  if (n <= 0 || bc <= 0 || d < 1 || d > 3 || m < -1 || n >= ((int64_t)1 << 31)) return VECCHIA_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  double w[3];
+  if (metric_weights(metric_scale, d, w)) return VECCHIA_EINVAL;
+  std::vector<int> hb(bc + 1);
+  PCHECK(hipMemcpyAsync(hb.data(), block_ptr, sizeof(int) * (bc + 1), hipMemcpyDeviceToHost, s));
+  PCHECK(hipStreamSynchronize(s));
+  if (hb[0] != 0 || hb[bc] > n) return VECCHIA_EINVAL;
+  return neighbors_impl(locs_perm, n, d, w, block_ptr, hb, bc, m, 0x7fffffff, nbr_ptr, nbr_idx, nbr_cap, workspace,
+                        ws_bytes, s);
+}
+
+// Prediction: the observations and the new locations side by side in the
+// workspace, the blocks shifted past the observations, every observation a
+// candidate of every block.
+namespace {
+struct PredNbrLayout {
+  size_t locs, bp, nbr, total;
+};
+PredNbrLayout pred_nbr_layout(int64_t n_obs, int64_t n_new, int64_t bc, int d) {
+  PredNbrLayout L;
+  const int64_t nt = n_obs + n_new;
+  size_t o = 0;
+  L.locs = o; o = al256(o + sizeof(double) * (size_t)nt * d);
+  L.bp = o;   o = al256(o + sizeof(int) * (size_t)(bc + 1));
+  L.nbr = o;  o = al256(o + nbr_layout(nt, max_cells(nt)).total);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+extern "C" size_t vecchia_pred_neighbors_workspace_size(int64_t n_obs, int64_t n_new, int64_t bc, int32_t d,
+                                                        int32_t m) {
+  (void)m;
+  if (n_obs <= 0 || n_new <= 0 || bc <= 0 || d < 1 || d > 3) return 0;
+  return pred_nbr_layout(n_obs, n_new, bc, d).total;
+}
+
+extern "C" int vecchia_pred_neighbors(const double* locs_obs, int64_t n_obs, const double* locs_new, int64_t n_new,
+                                      int32_t d, const double* metric_scale, const int32_t* block_ptr, int64_t bc,
+                                      int32_t m, int32_t* nbr_ptr, int32_t* nbr_idx, int64_t nbr_cap,
+                                      void* workspace, size_t ws_bytes, void* stream) {
+  if (!locs_obs || !locs_new || !block_ptr || !nbr_ptr || !nbr_idx || !workspace) return VECCHIA_EINVAL;
+  if (n_obs <= 0 || n_new <= 0 || bc <= 0 || bc > n_new || d < 1 || d > 3 || m < -1 ||
+      n_obs + n_new >= ((int64_t)1 << 31))
+    return VECCHIA_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  double w[3];
+  if (metric_weights(metric_scale, d, w)) return VECCHIA_EINVAL;
+  const PredNbrLayout L = pred_nbr_layout(n_obs, n_new, bc, d);
+  if (ws_bytes < L.total) return VECCHIA_ENOMEM;
+  std::vector<int> hb(bc + 1);
+  PCHECK(hipMemcpyAsync(hb.data(), block_ptr, sizeof(int) * (bc + 1), hipMemcpyDeviceToHost, s));
+  PCHECK(hipStreamSynchronize(s));
+  if (hb[0] != 0 || hb[bc] != n_new) return VECCHIA_EINVAL;
+  for (int64_t i = 0; i <= bc; ++i) hb[i] += (int)n_obs;
+  double* cat = at<double>(workspace, L.locs);
+  int* bp = at<int>(workspace, L.bp);
+  PCHECK(hipMemcpyAsync(cat, locs_obs, sizeof(double) * (size_t)n_obs * d, hipMemcpyDeviceToDevice, s));
+  PCHECK(hipMemcpyAsync(cat + (size_t)n_obs * d, locs_new, sizeof(double) * (size_t)n_new * d,
+                        hipMemcpyDeviceToDevice, s));
+  PCHECK(hipMemcpyAsync(bp, hb.data(), sizeof(int) * (bc + 1), hipMemcpyHostToDevice, s));
+  return neighbors_impl(cat, n_obs + n_new, d, w, bp, hb, bc, m, (int)n_obs, nbr_ptr, nbr_idx, nbr_cap,
+                        at<void>(workspace, L.nbr), ws_bytes - L.nbr, s);
 }

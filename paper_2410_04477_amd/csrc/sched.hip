@@ -9,11 +9,12 @@ namespace bv {
 // workload statistics (exact integer sums, so they are deterministic).
 __global__ void classify_kernel(const int* __restrict__ block_ptr, const int* __restrict__ nbr_ptr, int bc,
                                 int* __restrict__ cfg_of, int* __restrict__ counts, unsigned long long* __restrict__ stats,
-                                int* __restrict__ maxes, int* __restrict__ lmax_cfg, int engine) {
+                                int* __restrict__ maxes, int* __restrict__ lmax_cfg, int engine, int mpad) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= bc) return;
   const int l = block_ptr[b + 1] - block_ptr[b];
-  const int m = nbr_ptr[b + 1] - nbr_ptr[b];
+  const int m0 = nbr_ptr[b + 1] - nbr_ptr[b];
+  const int m = m0 < 0 ? m0 : (m0 + mpad - 1) / mpad * mpad;
   const int p = l + m;
   int c = engine == kEngineTiles ? cfg_for_joint(p) : cfg_mfma_for_joint(p);
   if (c < 0 && p <= 16383) c = kLargeCfg;   // served by the global-workspace kernel
@@ -137,9 +138,10 @@ namespace bv {
 static inline int cdiv(int a, int b) { return (a + b - 1) / b; }
 
 hipError_t launch_classify(const int* block_ptr, const int* nbr_ptr, int bc, int* cfg_of, int* counts,
-                           unsigned long long* stats, int* maxes, int* lmax_cfg, int engine, hipStream_t s) {
+                           unsigned long long* stats, int* maxes, int* lmax_cfg, int engine, int mpad,
+                           hipStream_t s) {
   hipLaunchKernelGGL(classify_kernel, dim3(cdiv(bc, 256)), dim3(256), 0, s, block_ptr, nbr_ptr, bc, cfg_of, counts,
-                     stats, maxes, lmax_cfg, engine);
+                     stats, maxes, lmax_cfg, engine, mpad);
   return hipGetLastError();
 }
 

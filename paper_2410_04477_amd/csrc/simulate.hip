@@ -120,7 +120,7 @@ extern "C" int vecchia_simulate(const double* locs_ord, int64_t n, int32_t d, co
   SCHECK(launch_fill_int(counts, 64, 0, s));
   int* lmax_cfg = maxes + 16;
   SCHECK(launch_fill_int(reinterpret_cast<int*>(stats), 16 + 16 + 32, 0, s));
-  SCHECK(launch_classify(bp, nbr_ptr, ni, cfg, counts, stats, maxes, lmax_cfg, kEngineMfmaWg, s));
+  SCHECK(launch_classify(bp, nbr_ptr, ni, cfg, counts, stats, maxes, lmax_cfg, kEngineMfmaWg, 1, s));
   int hc[32], hmax[4];
   SCHECK(hipMemcpyAsync(hc, counts, sizeof(hc), hipMemcpyDeviceToHost, s));
   SCHECK(hipMemcpyAsync(hmax, maxes, sizeof(hmax), hipMemcpyDeviceToHost, s));

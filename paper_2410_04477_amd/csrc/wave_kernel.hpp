@@ -93,7 +93,7 @@ __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
   // sdk, swk (P each) during the factorisation; for the adjoint, one chunk of
   // right-hand sides (P x (kWaveChunk + 1)), which also holds the G staged
   // diagonal tiles before the first chunk
-  return 3 * 16 * G + (mode == 0 || mode == 2 ? 7 * 16 * G
+  return 3 * 16 * G + (mode == 0 || mode == 2 || mode == 4 ? 7 * 16 * G
                                               : (16 * (kWaveChunk + 1) > kStageStride ? 16 * G * (kWaveChunk + 1)
                                                                                       : G * kStageStride));
 }
@@ -103,7 +103,11 @@ constexpr int wave_min_waves() { return sizeof(T) == 4 && (G <= 9 || MODE == 3) 
 
 // Modes: 0 value; 1 value and gradient in one launch; 2 value and the factor
 // tiles to the tile buffer; 3 gradient from those tiles (a second launch that
-// holds no tiles in registers, so it runs more waves per SIMD than mode 1).
+// holds no tiles in registers, so it runs more waves per SIMD than mode 1);
+// 4 prediction (Alg. 2): the block rows are new locations, the border row
+// carries y_N and zeros, and only the neighbour columns are eliminated, which
+// leaves the Schur complement -- the conditional covariance of the block and,
+// in the border row, minus its conditional mean -- in the trailing tiles.
 template <typename T, int G, int MODE>
 __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
   constexpr int P = 16 * G;
@@ -133,14 +137,28 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   const ThetaDev& th = thp.t[tt];
   const int b0 = a.block_ptr[b], b1 = a.block_ptr[b + 1];
   const int n0 = a.nbr_ptr[b], n1 = a.nbr_ptr[b + 1];
-  const int l = b1 - b0, m = n1 - n0, p = m + l;
+  const int l = b1 - b0, m = n1 - n0;
+  // prediction pads the neighbour rows with identity up to a panel boundary
+  const int mq = MODE == 4 ? pred_rows(m) : m;
+  const int p = mq + l;
+  // rows that hold a point (the rest of the P rows are identity padding)
+  auto real_row = [&](int i) __attribute__((always_inline)) { return i < p && (MODE != 4 || i < m || i >= mq); };
+  if (MODE == 4 && l == 0) return;
+  const double* org = (MODE == 4 ? a.locs2 : a.locs) + (size_t)b0 * a.d;   // coordinate origin: the block's first point
 
   for (int i = ln; i < P; i += 64) {
-    if (i < p) {
-      const int g = (i < m) ? a.nbr_idx[n0 + i] : (b0 + i - m);
-      if (MODE != 3) sy[i] = T(a.y[g]);
-      for (int k = 0; k < 3; ++k)
-        su[k * P + i] = k < a.d ? T((a.locs[(size_t)g * a.d + k] - a.locs[(size_t)b0 * a.d + k]) * th.inv_scale[k]) : T(0);
+    if (real_row(i)) {
+      const double* src;
+      if (MODE == 4) {
+        const bool nb = i < m;
+        src = nb ? a.locs + (size_t)a.nbr_idx[n0 + i] * a.d : a.locs2 + (size_t)(b0 + i - mq) * a.d;
+        sy[i] = nb ? T(a.y[a.nbr_idx[n0 + i]]) : T(0);   // the border row is [y_N, 0]
+      } else {
+        const int g = (i < m) ? a.nbr_idx[n0 + i] : (b0 + i - m);
+        src = a.locs + (size_t)g * a.d;
+        if (MODE != 3) sy[i] = T(a.y[g]);
+      }
+      for (int k = 0; k < 3; ++k) su[k * P + i] = k < a.d ? T((src[k] - org[k]) * th.inv_scale[k]) : T(0);
     } else {
       if (MODE != 3) sy[i] = T(0);
       for (int k = 0; k < 3; ++k) su[k * P + i] = T(0);
@@ -177,7 +195,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
         const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
         T v = sig2 * mc.rho(x) + ((i == j) ? nug : T(0));
-        if (!(i < p && j < p)) v = (i == j) ? T(1) : T(0);
+        if (!(real_row(i) && real_row(j))) v = (i == j) ? T(1) : T(0);
         acc[tix(I, J)][r] = -v;   // the tiles hold the negated matrix (updates add L L^T)
       }
       if (I == (p >> 4)) {  // border row p: y_J
@@ -266,13 +284,14 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     }
   };
 
+  const int kend = MODE == 4 ? mq : p;   // columns to eliminate
   static_for<0, G>(BV_CI(K) {
     BV_CV(K);
-    if (K * 16 >= p) return;
+    if (K * 16 >= kend) return;
 #pragma nounroll
     for (int c0 = 0; c0 < 16; c0 += 4) {
       const int k0 = K * 16 + c0;
-      if (k0 >= p) break;
+      if (k0 >= kend) break;
       publish(std::integral_constant<int, K>{}, c0);
       __syncthreads();
       factor_panel(k0);
@@ -289,7 +308,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
           acc[tix(I, J)] = M::op(v[I], v[J], acc[tix(I, J)]);
         });
       });
-      if (MODE != 0 && lr >= c0 && lr < c0 + 4) {
+      if (MODE != 0 && MODE != 4 && lr >= c0 && lr < c0 + 4) {
         // keep the finished factor columns in the tiles
         static_for<K, G>(BV_CI(I) {
           BV_CV(I);
@@ -300,6 +319,44 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       __syncthreads();
     }
   });
+
+  if constexpr (MODE == 4) {
+    // ---- prediction outputs from the trailing tiles (they hold -A) ------------
+    int bad = 0;
+    for (int k = ln; k < m; k += 64) bad |= !((double)sdk[k] > 0.0);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) bad |= __shfl_xor(bad, off, 64);
+    const double nanv = __builtin_nan("");
+    double* pm = a.out_mean + b0;
+    double* pv = a.out_var + b0;
+    double* pc = a.out_cov ? a.out_cov + (size_t)b * a.ldc * a.ldc : nullptr;
+    static_for<0, G>(BV_CI(I) {
+      BV_CV(I);
+      if (I * 16 > p) return;
+      static_for<0, I + 1>(BV_CI(J) {
+        BV_CV(J);
+        if (J * 16 + 15 < mq) return;
+        const int j = J * 16 + lr;
+        if (j < mq || j >= p) return;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = I * 16 + M::row(lg, r);
+          const double v = (double)acc[tix(I, J)][r];
+          if (i == p) {
+            pm[j - mq] = bad ? nanv : v;            // border row: -(-mu)
+          } else if (i >= j && i < p) {
+            const double c = bad ? nanv : -v;       // Schur complement: Sigma_B
+            if (i == j) pv[j - mq] = c;
+            if (pc) {
+              pc[(size_t)(i - mq) * a.ldc + (j - mq)] = c;
+              pc[(size_t)(j - mq) * a.ldc + (i - mq)] = c;
+            }
+          }
+        }
+      });
+    });
+    return;
+  }
 
   // ---- log-determinant, quadratic form and pivot guard (FP64) -----------------
   const double guard = a.fp32_guard == 2 ? INFINITY
@@ -580,7 +637,7 @@ static hipError_t launch_wave_g(const AdjArgs& a, const ThetaPack& thp, int grid
 
 template <typename T, int MODE>
 static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
-  if constexpr (MODE >= 2) {   // split gradient: only the classes that use it
+  if constexpr (MODE == 2 || MODE == 3) {   // split gradient: only the classes that use it
     if (g == 10) return launch_wave_g<T, 10, MODE>(a, thp, grid, s);
     if (g == 11) return launch_wave_g<T, 11, MODE>(a, thp, grid, s);
     return hipErrorInvalidValue;
