@@ -61,6 +61,7 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-prediction", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (HBM counter calibration under rocprofv3)")
     ap.add_argument("--print-sha", action="store_true", help="print the kernel source hash and exit")
@@ -85,17 +86,23 @@ def main() -> int:
     t_setup = time.perf_counter()
 
     # ---- synthetic data: sequential Vecchia draw (sim_m neighbours) ----------
+    # n_new held-out locations are drawn after the n observed ones in the
+    # simulation order, so the observed values do not depend on them
     locs = W.locations(w)
+    n_new = 0 if args.no_prediction else w.n // 10
+    locs_new = W.new_locations(w, n_new)
     order = W.point_permutation(w.n, w.seed_y)
     inv_order = np.argsort(order)
     metric = list(w.metric_scale)
-    locs_ord = torch.tensor(locs[order], device=dev)
-    unit = torch.arange(w.n + 1, dtype=torch.int32, device=dev)
-    log(f"simulating y: n={w.n}, {w.sim_m} neighbours")
+    locs_ord = torch.tensor(np.vstack([locs[order], locs_new]), device=dev)
+    unit = torch.arange(w.n + n_new + 1, dtype=torch.int32, device=dev)
+    log(f"simulating y: n={w.n} (+{n_new} held out), {w.sim_m} neighbours")
     snptr, snidx = api.neighbors(locs_ord, unit, w.sim_m, metric)
-    z = torch.tensor(W.standard_normal(w.n, w.seed_y), device=dev)
+    z = torch.tensor(np.concatenate([W.standard_normal(w.n, w.seed_y), W.standard_normal(n_new, w.seed_y + 1)]),
+                     device=dev)
     y_ord = api.simulate(locs_ord, snptr, snidx, (th0.sigma2, th0.beta, th0.nugget, th0.nu, th0.aniso), z)
-    y = api.permute_rows(y_ord, torch.tensor(inv_order, device=dev))
+    y = api.permute_rows(y_ord[:w.n].contiguous(), torch.tensor(inv_order, device=dev))
+    y_new = y_ord[w.n:].contiguous()
     del snptr, snidx, locs_ord, unit, y_ord, z
     torch.cuda.synchronize()
     t_sim = time.perf_counter() - t_setup
@@ -216,6 +223,11 @@ def main() -> int:
                 "grad_err_per_component_vs_sum_abs_block_terms": [float(v) for v in np.abs(g32n - g64n) / gscale],
                 "fp32_blocks_refactored": int(c32[0, 0]), "blocks": int(plan.bc)}
 
+    # ---- prediction (Alg. 2) and conditional simulation at the held-out points --
+    prediction = None
+    if n_new > 0:
+        prediction = bench_prediction(model, locs_new, y_new, w, th0, metric, args.steps, dev)
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same blocks --
     cpu = None
     if not args.no_cpu_baseline:
@@ -247,6 +259,7 @@ def main() -> int:
         "variants": variants,
         "accuracy": accuracy,
         "setup_s": {"simulate": t_sim, "preprocess": t_pre},
+        "prediction": prediction,
     }
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -257,6 +270,83 @@ def main() -> int:
         out["copy_calibration_bytes"] = 2 * src.numel() * 8
     print(json.dumps(out), flush=True)
     return 0
+
+
+def pred_flops(m, l):
+    """Algorithmic flops of one prediction block: Cholesky of the neighbour
+    covariance (m^3/3), the triangular solves of K_NB and y_N (m^2 (l + 1)),
+    the Schur update (m (l + 1)^2) and covariance generation (30 per entry)."""
+    p = m + l
+    return m ** 3 / 3.0 + m * m * (l + 1) + m * (l + 1) ** 2 + 30.0 * p * (p + 1) / 2.0
+
+
+def bench_prediction(model, locs_new, y_new, w, th0, metric, steps, dev):
+    """Block Vecchia prediction at n_new held-out points of the same field
+    (blocks of about 10 new points, the workload's m observed neighbours each),
+    then 1,000 rounds of univariate conditional simulation with PICP and MSPE."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2410_04477_amd import api
+
+    n_new = locs_new.shape[0]
+    bc = n_new // 10
+    t0 = time.perf_counter()
+    ln = torch.tensor(locs_new, device=dev)
+    perm, bp, _ = api.blocks(ln, bc, torch.tensor(W.kmeans_init(n_new, bc, w.seed_kmeans + 7), device=dev),
+                             torch.tensor(W.block_permutation(bc, w.seed_kmeans + 7), device=dev), metric)
+    ln = api.permute_rows(ln, perm)
+    yt = api.permute_rows(y_new, perm)
+    npt, nid = api.pred_neighbors(model.locs_perm, ln, bp, w.m, metric)
+    plan = api.Plan(bp, npt, n_new, 1, "mfma", predict=True)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+    th = (th0.sigma2, th0.beta, th0.nugget, th0.nu, th0.aniso)
+    for _ in range(2):
+        api.predict(plan, model.locs_perm, model.y_perm, ln, nid, th)
+    torch.cuda.synchronize()
+    plan.set_timing(True)
+    plan.timing(reset=True)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        mean, var, _ = api.predict(plan, model.locs_perm, model.y_perm, ln, nid, th)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    kt = plan.timing(reset=True)
+    plan.set_timing(False)
+    nq = int(plan.c.nbuckets)
+    span_s = kt[nq][0] / kt[nq][1] / 1e3
+    l = np.diff(plan.block_ptr.cpu().numpy()).astype(np.float64)
+    m = np.diff(plan.nbr_ptr.cpu().numpy()).astype(np.float64)
+    flops = float(np.sum(pred_flops(m, l)))
+    gs = [int(plan.c.bucket_cfg[q]) + 1 for q in range(nq)]
+    # conditional simulation: the random numbers are drawn on the device (seeded)
+    R = 1000
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(w.seed_y + 2)
+    z = torch.randn((R, n_new), generator=gen, dtype=torch.float64, device=dev)
+    api.condsim(mean, var, z, yt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 5
+    for _ in range(reps):
+        cs = api.condsim(mean, var, z, yt)
+    torch.cuda.synchronize()
+    t_cs = (time.perf_counter() - t0) / reps
+    cs_bytes = R * n_new * 8.0 + 7.0 * n_new * 8   # z once; mean, var, truth in; four outputs
+    return {"workload": f"{n_new} held-out points of the same field, {bc} K-means blocks, m={w.m} observed "
+                        f"neighbours of {w.n}, FP64",
+            "n_new": n_new, "bc": bc, "m": w.m, "ms": wall * 1e3, "points_per_s": n_new / wall,
+            "roofline": {"bound": "mfma", "achieved": flops / span_s / 1e12, "peak": FP64_PEAK / 1e12,
+                         "unit": "TFLOP/s", "frac": flops / span_s / FP64_PEAK,
+                         "kernel": ", ".join(f"bv_wave_kernel<double,{g},4>" for g in gs),
+                         "avg_launch_ms": span_s * 1e3, "flops_per_launch": flops},
+            "condsim": {"rounds": R, "ms": t_cs * 1e3, "picp": cs["picp"], "mspe": cs["mspe"],
+                        "mean_pred_var": float(var.mean()),
+                        "roofline": {"bound": "hbm", "achieved": cs_bytes / t_cs / 1e9, "peak": 8000.0,
+                                     "unit": "GB/s", "frac": cs_bytes / t_cs / 8e12}},
+            "setup_s": t_pre}
 
 
 def cpu_baseline(model, plan, bp, npt, th0, target_s):

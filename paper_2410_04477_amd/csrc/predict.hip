@@ -8,38 +8,60 @@
 namespace bv {
 
 constexpr double kZ975 = 1.959963984540054;   // standard normal quantile at 0.975
-constexpr int kCondsimBlocks = 1024;
+constexpr int kCondsimBlocks = 4096;
+constexpr int kSlices = 4;   // waves per workgroup, each summing every kSlices-th draw
 
-// One thread per location (grid-stride); z is read coalesced, draw r of
-// location j at z[r * n + j].  Two passes over the draws (mean, then squared
-// deviations).  Per-workgroup coverage counts and squared errors go to part.
+// A workgroup takes 64 consecutive locations; wave k of it sums the draws
+// r = k, k + kSlices, ... (one coalesced 512-byte row of z per step), so the
+// R x n draws are read once with four times the waves in flight.  The draws
+// are summed shifted by the mean (d = sqrt(var) z): sample mean
+// mean + sum d / R, sample variance (sum d^2 - (sum d)^2 / R) / (R - 1).
+// Per-workgroup coverage counts and squared errors go to part.
 __global__ void __launch_bounds__(256)
 condsim_kernel(const double* __restrict__ mean, const double* __restrict__ var, int64_t n,
                const double* __restrict__ z, int R, const double* __restrict__ y_true, double* __restrict__ smean,
                double* __restrict__ ssd, double* __restrict__ lo, double* __restrict__ hi, double* __restrict__ part) {
+  __shared__ double s1s[kSlices][64], s2s[kSlices][64];
   __shared__ double s_in[256], s_err[256];
+  const int lane = threadIdx.x & 63, slice = threadIdx.x >> 6;
   double in_acc = 0.0, err_acc = 0.0;
-  for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < n; j += (int64_t)gridDim.x * 256) {
-    const double mu = mean[j], sd = sqrt(var[j]);
-    double acc = 0.0;
-    for (int r = 0; r < R; ++r) acc += mu + sd * z[(size_t)r * n + j];
-    const double m = acc / (double)R;
-    double ss = 0.0;
-    for (int r = 0; r < R; ++r) {
-      const double dv = (mu + sd * z[(size_t)r * n + j]) - m;
-      ss += dv * dv;
+  for (int64_t base = (int64_t)blockIdx.x * 64; base < n; base += (int64_t)gridDim.x * 64) {
+    const int64_t j = base + lane;
+    double a1 = 0.0, a2 = 0.0;
+    if (j < n) {
+      const double sd = sqrt(var[j]);
+      const double* zj = z + j;
+#pragma unroll 8
+      for (int r = slice; r < R; r += kSlices) {
+        const double dv = sd * zj[(size_t)r * n];
+        a1 += dv;
+        a2 += dv * dv;
+      }
     }
-    const double sdv = sqrt(ss / (double)(R - 1));
-    const double l = m - kZ975 * sdv, h = m + kZ975 * sdv;
-    if (smean) smean[j] = m;
-    if (ssd) ssd[j] = sdv;
-    if (lo) lo[j] = l;
-    if (hi) hi[j] = h;
-    if (y_true) {
-      const double yt = y_true[j];
-      in_acc += (yt >= l && yt <= h) ? 1.0 : 0.0;
-      err_acc += (m - yt) * (m - yt);
+    s1s[slice][lane] = a1;
+    s2s[slice][lane] = a2;
+    __syncthreads();
+    if (slice == 0 && j < n) {
+      double t1 = 0.0, t2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < kSlices; ++k) {
+        t1 += s1s[k][lane];
+        t2 += s2s[k][lane];
+      }
+      const double m = mean[j] + t1 / (double)R;
+      const double sdv = sqrt(fmax(t2 - t1 * t1 / (double)R, 0.0) / (double)(R - 1));
+      const double l = m - kZ975 * sdv, h = m + kZ975 * sdv;
+      if (smean) smean[j] = m;
+      if (ssd) ssd[j] = sdv;
+      if (lo) lo[j] = l;
+      if (hi) hi[j] = h;
+      if (y_true) {
+        const double yt = y_true[j];
+        in_acc += (yt >= l && yt <= h) ? 1.0 : 0.0;
+        err_acc += (m - yt) * (m - yt);
+      }
     }
+    __syncthreads();
   }
   s_in[threadIdx.x] = in_acc;
   s_err[threadIdx.x] = err_acc;
@@ -96,7 +118,7 @@ extern "C" int vecchia_condsim(const double* mean, const double* var, int64_t n,
   if (!mean || !var || !z || !workspace || n <= 0 || R < 2 || (y_true && !stats)) return VECCHIA_EINVAL;
   if (ws_bytes < vecchia_condsim_workspace_size(n)) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
-  const int64_t want = (n + 255) / 256;
+  const int64_t want = (n + 63) / 64;
   const int nb = (int)(want < kCondsimBlocks ? want : kCondsimBlocks);
   double* part = static_cast<double*>(workspace);
   hipLaunchKernelGGL(condsim_kernel, dim3(nb), dim3(256), 0, s, mean, var, n, z, (int)R, y_true, smean, ssd, lo, hi,

@@ -94,6 +94,16 @@ def locations(w: Workload) -> np.ndarray:
     return s
 
 
+def new_locations(w: Workload, n_new: int) -> np.ndarray:
+    """n_new x d prediction locations from the same distribution as locations(w)
+    (an independent seed)."""
+    g = rng(w.seed_locs + 500)
+    s = g.random((n_new, w.d))
+    if w.d == 3:
+        s[:, 2] *= w.zmax
+    return s
+
+
 def standard_normal(n: int, seed: int) -> np.ndarray:
     """Innovations for simulators (N(0,1), float64)."""
     return rng(seed).standard_normal(n)
