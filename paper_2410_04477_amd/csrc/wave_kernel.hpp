@@ -255,8 +255,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     for (int q = 0; q < (P + 63) / 64; ++q) {
       const int i = i0 + ln + 64 * q;
       if (i < P) {
-        // branch-free: every lane runs the substitution, then rows above the
-        // block take zero and rows inside it take L_dd
+        // branch-free: every lane runs the substitution, which also yields the
+        // rows of the diagonal block up to their diagonal (the operations that
+        // formed Ld); right of the diagonal there, and above the block, is zero
         const int di = i - k0;
         T x[4];
 #pragma unroll
@@ -264,11 +265,8 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
           T v = -pan[c * P + i];
 #pragma unroll
           for (int j = 0; j < c; ++j) v -= x[j] * Ld[c][j];
-          const T t = (k0 + c < p) ? v * rinv[c] : T(0);
-          T v2 = t;
-#pragma unroll
-          for (int rr = 0; rr < 4; ++rr) v2 = di == rr ? Ld[rr][c] : v2;
-          x[c] = di < 0 ? T(0) : v2;
+          const T t = di < c ? T(0) : v * rinv[c];
+          x[c] = (k0 + c < p) ? t : (di == c ? T(1) : T(0));   // padding columns: identity
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) pan[c * P + i] = x[c];
@@ -590,18 +588,26 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         const int j = J * 16 + lr;
         const T sj0 = su[j], sj1 = su[P + j], sj2 = su[2 * P + j];
         T s0 = T(0), s1 = T(0), s2 = T(0);
+        auto entry = [&](int r) __attribute__((always_inline)) {
+          const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
+          const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
+          T rho, drho;
+          mc.rho_drange(x, irange, rho, drho);
+          s0 += c[r] * rho;
+          s1 += c[r] * drho;
+        };
+        if ((I + 1) * 16 <= p) {   // a tile inside the point rows (wave-uniform)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int i = I * 16 + M::row(lg, r);
-          if (i < p && j < p) {
-            const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
-            const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
-            T rho, drho;
-            mc.rho_drange(x, irange, rho, drho);
-            s0 += c[r] * rho;
-            s1 += c[r] * drho;
-            if (i == j) s2 += c[r];
-          }
+          for (int r = 0; r < 4; ++r) entry(r);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (I * 16 + M::row(lg, r) < p && j < p) entry(r);
+        }
+        if (I == J) {   // d K / d nugget is the identity
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (M::row(lg, r) == lr && j < p) s2 += c[r];
         }
         const double wgt = I == J ? 1.0 : 2.0;
         g0 += wgt * (double)s0;
