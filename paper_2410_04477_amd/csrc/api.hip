@@ -283,7 +283,7 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 // 1: value + gradient.  VECCHIA_EUNSUPPORTED when the four-wave adjoint's
 // right-hand sides do not fit the device LDS.
 static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mode, AdjArgs a, const ThetaPack& thp,
-                             int grid, hipStream_t s, void* tiles, size_t tile_bytes) {
+                             int grid, hipStream_t s, void* tiles, size_t tile_bytes, hipStream_t s2 = nullptr) {
   const int g = plan->bucket_cfg[q] + 1;
   if (plan->engine == kEngineMfma && wave_fits(g, fp32)) {
     if (mode == 0) {
@@ -295,6 +295,21 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
     const size_t cap = tile_bytes / per;
     if (cap == 0) return VECCHIA_ENOMEM;
     const int chunk = cap < (size_t)grid ? (int)cap : grid;
+    if (s2 && wave_split(g, fp32) && chunk == grid && grid >= 2) {
+      // the split gradient in two halves on two streams: the adjoint launch of
+      // one half overlaps the factorisation launch of the other, each half
+      // with its own part of the tile buffer
+      const int h = (grid + 1) / 2;
+      for (int k = 0; k < 2; ++k) {
+        a.item_base = k ? h : 0;
+        a.tiles = static_cast<char*>(tiles) + (k ? (size_t)h * per : 0);
+        const int n = k ? grid - h : h;
+        const hipStream_t sk = k ? s2 : s;
+        VCHECK_HIP(launch_wave(g, fp32, 2, a, thp, n, sk));
+        VCHECK_HIP(launch_wave(g, fp32, 3, a, thp, n, sk));
+      }
+      return VECCHIA_OK;
+    }
     a.tiles = tiles;
     for (int w0 = 0; w0 < grid; w0 += chunk) {
       a.item_base = w0;
@@ -335,6 +350,13 @@ static hipStream_t class_stream(const vecchia_plan* plan, int q, hipStream_t s, 
   if (!conc || q == plan->bucket_main) return s;
   const int k = (q < plan->bucket_main ? q : q - 1) % kSideStreams;
   return static_cast<Exec*>(plan->exec)->side[k];
+}
+// A side stream that no size class uses (the last one, when the classes other
+// than the largest leave it free), or null.
+static hipStream_t spare_stream(const vecchia_plan* plan, int q) {
+  if (!plan->exec || plan->nbuckets - 1 >= kSideStreams) return nullptr;
+  (void)q;
+  return static_cast<Exec*>(plan->exec)->side[kSideStreams - 1];
 }
 static hipError_t fork_streams(const vecchia_plan* plan, hipStream_t s) {
   Exec* ex = static_cast<Exec*>(plan->exec);
@@ -651,7 +673,8 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
         VCHECK_ST(launch_tiles_adjoint(plan, q, fp32, a, thp, ns * nt, sq));
       else if (conc)
         VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq,
-                                    static_cast<char*>(plan->aux_ws) + off[q], off[q + 1] - off[q]));
+                                    static_cast<char*>(plan->aux_ws) + off[q], off[q + 1] - off[q],
+                                    spare_stream(plan, q)));
       else
         VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq, plan->aux_ws, plan->aux_ws_bytes));
       VCHECK_HIP(time_end(plan, sq, tr));

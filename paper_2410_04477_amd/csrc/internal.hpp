@@ -70,7 +70,10 @@ size_t mfma_lds_need(int g, bool fp32, int mode, int ldx);   // dynamic LDS byte
 // exceed the register file and part of them spills to scratch)
 constexpr int kWaveMaxG32 = 11;
 constexpr int kWaveMaxG64 = 11;
-constexpr int kWaveChunk = 32;  // adjoint right-hand sides per pass (bounds the LDS of any block)
+constexpr int kWaveChunk = 32;  // adjoint right-hand sides per pass, at most (bounds the LDS of any block)
+// right-hand sides per pass of a class with g tile rows: 28 up to g = 9, which
+// keeps the one-wave adjoint's LDS at or under 20 kB (eight waves per CU)
+__host__ __device__ constexpr int wave_chunk(int g) { return g <= 9 ? 28 : kWaveChunk; }
 // bytes of one work item's factor tiles in the adjoint's tile buffer, and the buffer's cap
 inline size_t wave_tile_bytes(int g, bool fp32) { return (size_t)g * (g + 1) / 2 * 256 * (fp32 ? 4 : 8); }
 constexpr size_t kAdjTileCap = (size_t)4 << 30;

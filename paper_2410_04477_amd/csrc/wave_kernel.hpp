@@ -91,11 +91,13 @@ constexpr int kStageStride = 260;   // staged 16 x 16 tiles, padded so tiles fou
 __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
   // su (3 P) for the whole kernel, then a work region: the panel (4 P) and sy,
   // sdk, swk (P each) during the factorisation; for the adjoint, one chunk of
-  // right-hand sides (P x (kWaveChunk + 1)), which also holds the G staged
+  // right-hand sides (P x (wave_chunk(G) + 1), plus 32 elements that reads of
+  // the last row's unused columns may touch), which also holds the G staged
   // diagonal tiles before the first chunk
   return 3 * 16 * G + (mode == 0 || mode == 2 || mode == 4 ? 7 * 16 * G
-                                              : (16 * (kWaveChunk + 1) > kStageStride ? 16 * G * (kWaveChunk + 1)
-                                                                                      : G * kStageStride));
+                                              : (16 * (wave_chunk(G) + 1) > kStageStride
+                                                     ? 16 * G * (wave_chunk(G) + 1) + 32
+                                                     : G * kStageStride));
 }
 
 template <typename T, int G, int MODE>
@@ -395,7 +397,11 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     flag = a.flag[o];   // written by the factorisation launch
   }
 
-  constexpr int LDX = kWaveChunk + 1;
+  constexpr int CH = wave_chunk(G);   // right-hand sides per pass
+  constexpr int LDX = CH + 1;
+  // with CH < 32 the second 16-column tile is partly outside a row: its reads
+  // there are harmless (other columns of the MFMA results), its writes masked
+  const bool colok = CH == 32 || 16 + lr < CH;
   constexpr int GM = G > 1 ? G - 1 : 1;   // tile rows above a diagonal step, at most
   const int nr = l + 2;
   const int Ip = p >> 4, rp = p & 15;
@@ -460,14 +466,14 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   }
   __syncthreads();
 
-  // ---- X <- L^-T X and the contraction, kWaveChunk right-hand sides per pass --
+  // ---- X <- L^-T X and the contraction, CH right-hand sides per pass ---------
   const T irange = T(th.inv_range);
   double g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int cb = 0; cb < nr; cb += kWaveChunk) {
-    const int nc = nr - cb < kWaveChunk ? nr - cb : kWaveChunk;
+  for (int cb = 0; cb < nr; cb += CH) {
+    const int nc = nr - cb < CH ? nr - cb : CH;
     const int nq = (nc + 15) >> 4;
     __syncthreads();
-    for (int e = ln; e < P * LDX; e += 64) X[e] = T(0);
+    for (int e = ln; e < P * LDX + 32; e += 64) X[e] = T(0);
     __syncthreads();
     // column cb + c of [ w | [z; 0] | [0; I_l] ]
     for (int c = ln; c < nc; c += 64)
@@ -510,7 +516,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 2; ++q)
-        if (q < nq) {
+        if (q < nq && (q == 0 || colok)) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) X[(K * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = dq[q][r];
         }
@@ -545,7 +551,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
           if (J < K) {
 #pragma unroll
             for (int q = 0; q < 2; ++q)
-              if (q < nq) {
+              if (q < nq && (q == 0 || colok)) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = cj[J][q][r];
               }
@@ -558,9 +564,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     // the next tile's MFMA chain is issued before this tile's contraction
     const int nk = (nc + 3) >> 2;
     for (int I = 0; I < Gp; ++I) {
-      T av[kWaveChunk / 4];
+      T av[CH / 4];
 #pragma unroll
-      for (int kq = 0; kq < kWaveChunk / 4; ++kq) {
+      for (int kq = 0; kq < CH / 4; ++kq) {
         const int q = 4 * kq + lg;
         av[kq] = (cb + q == 0 ? T(1) : T(-1)) * X[(I * 16 + lr) * LDX + q];
       }
@@ -577,7 +583,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 #pragma unroll
         for (int r = 0; r < 4; ++r) c[r] = T(0);
 #pragma unroll
-        for (int kq = 0; kq < kWaveChunk / 4; ++kq)
+        for (int kq = 0; kq < CH / 4; ++kq)
           if (kq < nk) c = M::op(av[kq], X[(J * 16 + lr) * LDX + 4 * kq + lg], c);
         return c;
       };
