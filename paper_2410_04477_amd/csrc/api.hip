@@ -299,12 +299,13 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
       // the split gradient in two halves on two streams: the adjoint launch of
       // one half overlaps the factorisation launch of the other, each half
       // with its own part of the tile buffer
-      const int h = (grid + 1) / 2;
-      for (int k = 0; k < 2; ++k) {
-        a.item_base = k ? h : 0;
-        a.tiles = static_cast<char*>(tiles) + (k ? (size_t)h * per : 0);
-        const int n = k ? grid - h : h;
-        const hipStream_t sk = k ? s2 : s;
+      constexpr int kPieces = 2;
+      const int h = (grid + kPieces - 1) / kPieces;
+      for (int k = 0; k * h < grid; ++k) {
+        a.item_base = k * h;
+        a.tiles = static_cast<char*>(tiles) + (size_t)k * h * per;
+        const int n = grid - k * h < h ? grid - k * h : h;
+        const hipStream_t sk = (k & 1) ? s2 : s;
         VCHECK_HIP(launch_wave(g, fp32, 2, a, thp, n, sk));
         VCHECK_HIP(launch_wave(g, fp32, 3, a, thp, n, sk));
       }
