@@ -37,6 +37,18 @@ def rho(x, nu: float):
     return rho_general(x, nu)
 
 
+def drho_dbeta_general(x, beta: float, nu: float):
+    """d rho(h/beta) / d beta for any nu > 0.  With the Bessel identity
+    d/dx [x^nu K_nu(x)] = -x^nu K_(nu-1)(x), rho'(x) = -2^(1-nu)/Gamma(nu)
+    x^nu K_(nu-1)(x), and d rho / d beta = rho'(x) * (-x / beta)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    pos = x > 0
+    xp = x[pos]
+    out[pos] = (xp / beta) * (2.0 ** (1.0 - nu) / special.gamma(nu)) * xp ** nu * special.kv(nu - 1.0, xp)
+    return out
+
+
 def drho_dbeta(x, beta: float, nu: float):
     """d rho(h/beta) / d beta = rho'(x) * (-x / beta)."""
     x = np.asarray(x, dtype=np.float64)
@@ -48,7 +60,7 @@ def drho_dbeta(x, beta: float, nu: float):
     elif nu == 2.5:
         g = (x / 3.0) * (1.0 + x) * e
     else:
-        raise ValueError("derivative only for nu in {0.5, 1.5, 2.5}")
+        return drho_dbeta_general(x, beta, nu)
     return (x / beta) * g
 
 

@@ -158,3 +158,35 @@ def test_gradient_matches_fd_and_numpy(theta):
         lm_ = coracle.loglik(*args, theta.replace(**{name: v - h}))
         fd.append((lp_ - lm_) / (2 * h))
     np.testing.assert_allclose(g, fd, rtol=2e-5, atol=1e-6 * np.abs(g).max())
+
+
+@pytest.mark.parametrize("nu", [0.3, 0.8, 1.0, 2.0, 3.3])
+def test_general_nu_numpy_oracle(nu):
+    """Any nu > 0 through the Bessel form: all-previous conditioning equals
+    the exact GP density, the block term is the joint minus the neighbour
+    log-pdf (library multivariate normal), and the trace-formula gradient
+    matches central differences."""
+    theta = W.Theta(1.1, 0.08, 2e-3, nu)
+    s, y, pre = _problem(90, 9, -1, theta)
+    lp, yp = pre["locs_perm"], y[pre["perm"]]
+    args = (lp, yp, pre["block_ptr"], pre["nbr_ptr"], pre["nbr_idx"])
+    assert OL.loglik(*args, theta) == pytest.approx(OL.exact_loglik(lp, yp, theta), rel=1e-11)
+    s, y, pre = _problem(90, 9, 12, theta)
+    lp, yp = pre["locs_perm"], y[pre["perm"]]
+    args = (lp, yp, pre["block_ptr"], pre["nbr_ptr"], pre["nbr_idx"])
+    terms = OL.block_terms(*args, theta)
+    bp, npt, nid = pre["block_ptr"], pre["nbr_ptr"], pre["nbr_idx"]
+    for i in (0, 4, 8):
+        nn = nid[npt[i]:npt[i + 1]]
+        sj = np.vstack([lp[nn], lp[bp[i]:bp[i + 1]]])
+        kj = matern.cov(sj, sj, theta, same=True)
+        yj = np.concatenate([yp[nn], yp[bp[i]:bp[i + 1]]])
+        ref = stats.multivariate_normal(np.zeros(yj.size), kj).logpdf(yj)
+        if nn.size:
+            ref -= stats.multivariate_normal(np.zeros(nn.size), kj[:nn.size, :nn.size]).logpdf(yp[nn])
+        assert terms[i] == pytest.approx(ref, rel=1e-10)
+    g = OL.grad_trace(*args, theta).sum(0)
+    for k, name in enumerate(("sigma2", "beta", "nugget")):
+        v, h = getattr(theta, name), 1e-6 * max(getattr(theta, name), 1e-3)
+        fd = (OL.loglik(*args, theta.replace(**{name: v + h})) - OL.loglik(*args, theta.replace(**{name: v - h}))) / (2 * h)
+        assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-6)

@@ -58,3 +58,18 @@ def test_nugget_only_on_same_index_and_anisotropy():
     # per-axis range beta*aniso: dx = 0.2 over 0.05, dz = 0.01 over 0.01
     x = np.sqrt((0.2 / 0.05) ** 2 + (0.01 / 0.01) ** 2)
     assert K[0, 2] == pytest.approx(2.0 * np.exp(-x), rel=1e-14)
+
+
+@pytest.mark.parametrize("nu", [0.2, 0.5, 0.8, 1.0, 1.5, 2.0, 2.5, 3.7])
+def test_general_derivative_matches_fd_and_closed_forms(nu):
+    """The Bessel form of d rho / d beta against central differences of the
+    Bessel form of rho, and against the closed forms at half-integer nu."""
+    h = np.array([0.003, 0.01, 0.05, 0.2, 0.6, 2.0])
+    beta = 0.07
+    eps = 1e-7
+    fd = (matern.rho_general(h / (beta + eps), nu) - matern.rho_general(h / (beta - eps), nu)) / (2 * eps)
+    got = matern.drho_dbeta_general(h / beta, beta, nu)
+    np.testing.assert_allclose(got, fd, rtol=2e-6, atol=1e-12)
+    if nu in (0.5, 1.5, 2.5):
+        np.testing.assert_allclose(got, matern.drho_dbeta(h / beta, beta, nu), rtol=1e-12)
+        np.testing.assert_allclose(matern.rho_general(h / beta, nu), matern.rho(h / beta, nu), rtol=1e-12)
