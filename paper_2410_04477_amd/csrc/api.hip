@@ -53,28 +53,50 @@ PlanLayout plan_layout(int64_t bc, int32_t max_theta) {
   return L;
 }
 
-bool theta_to_dev(const vecchia_theta& t, int d, ThetaDev& o) {
+// Orders of the Bessel form: nu in [kNuMin, kNuMax] (outside the closed forms).
+constexpr double kNuMin = 0.05, kNuMax = 10.0;
+
+// VECCHIA_OK, VECCHIA_EINVAL (bad value) or VECCHIA_EUNSUPPORTED (nu outside
+// what the kernels evaluate).
+int theta_status(const vecchia_theta& t, int d, ThetaDev& o) {
+  memset(&o, 0, sizeof(o));
   if (!(t.sigma2 > 0) || !(t.range > 0) || !(t.nugget >= 0) || !isfinite(t.sigma2) || !isfinite(t.range) ||
-      !isfinite(t.nugget))
-    return false;
-  if (t.nu == 0.5) o.nu_code = 0;
-  else if (t.nu == 1.5) o.nu_code = 1;
-  else if (t.nu == 2.5) o.nu_code = 2;
-  else return false;
+      !isfinite(t.nugget) || !(t.nu > 0) || !isfinite(t.nu))
+    return VECCHIA_EINVAL;
+  if (!(t.nu >= kNuMin && t.nu <= kNuMax)) return VECCHIA_EUNSUPPORTED;
+  o.nu_code = t.nu == 0.5 ? 0 : t.nu == 1.5 ? 1 : t.nu == 2.5 ? 2 : 3;
+  {
+    // order-only constants of the Bessel form, also for the closed-form orders
+    // (a launch that holds any other nu evaluates all its thetas that way):
+    // mu = nu - n, |mu| <= 1/2, Temme's Gamma1(mu) = (1/Gamma(1-mu) -
+    // 1/Gamma(1+mu)) / (2 mu) and Gamma2(mu) = their mean; for small mu,
+    // Gamma1 from the Taylor series of 1/Gamma(1+z) (Abramowitz and Stegun
+    // 6.1.34), which avoids the cancellation
+    o.nu_n = (int)floor(t.nu + 0.5);
+    const double mu = t.nu - o.nu_n;
+    o.nu_mu = mu;
+    o.nu_gampl = 1.0 / tgamma(1.0 + mu);
+    o.nu_gammi = 1.0 / tgamma(1.0 - mu);
+    o.nu_gam2 = 0.5 * (o.nu_gammi + o.nu_gampl);
+    o.nu_gam1 = fabs(mu) < 1e-3 ? -(0.5772156649015329 - 0.0420026350340952 * mu * mu)
+                                : (o.nu_gammi - o.nu_gampl) / (2.0 * mu);
+    o.nu_lognorm = (1.0 - t.nu) * log(2.0) - lgamma(t.nu);
+  }
   o.sigma2 = t.sigma2;
   o.nugget = t.nugget;
   o.inv_range = 1.0 / t.range;
   for (int k = 0; k < 3; ++k) {
     if (k < d) {
-      if (!(t.aniso[k] > 0)) return false;
+      if (!(t.aniso[k] > 0) || !isfinite(t.aniso[k])) return VECCHIA_EINVAL;
       o.inv_scale[k] = 1.0 / (t.range * t.aniso[k]);
     } else {
       o.inv_scale[k] = 0.0;
     }
   }
-  o.pad_ = 0;
-  return true;
+  return VECCHIA_OK;
 }
+
+bool theta_to_dev(const vecchia_theta& t, int d, ThetaDev& o) { return theta_status(t, d, o) == VECCHIA_OK; }
 
 template <typename P> P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(base) + off); }
 
@@ -285,6 +307,8 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mode, AdjArgs a, const ThetaPack& thp,
                              int grid, hipStream_t s, void* tiles, size_t tile_bytes, hipStream_t s2 = nullptr) {
   const int g = plan->bucket_cfg[q] + 1;
+  a.gen = 0;
+  for (int t = 0; t < a.ntheta; ++t) a.gen |= thp.t[t].nu_code == 3;
   if (plan->engine == kEngineMfma && wave_fits(g, fp32)) {
     if (mode == 0) {
       VCHECK_HIP(launch_wave(g, fp32, 0, a, thp, grid, s));
@@ -503,9 +527,10 @@ static int check_common(const vecchia_plan* plan, const double* locs, const doub
     return VECCHIA_EINVAL;
   for (int t = 0; t < ntheta; ++t) {
     ThetaDev td;
-    if (!theta_to_dev(theta[t], d, td)) return (theta[t].nu == 0.5 || theta[t].nu == 1.5 || theta[t].nu == 2.5)
-                                                   ? VECCHIA_EINVAL
-                                                   : VECCHIA_EUNSUPPORTED;
+    const int st = theta_status(theta[t], d, td);
+    if (st) return st;
+    // the Bessel form is evaluated by the one-wave kernels only
+    if (td.nu_code == 3 && (plan->engine != kEngineMfma || plan->nlarge > 0)) return VECCHIA_EUNSUPPORTED;
   }
   return VECCHIA_OK;
 }
@@ -728,8 +753,8 @@ extern "C" int vecchia_predict(const vecchia_plan* plan, const double* locs_obs,
   if (d < 1 || d > 3 || (cov && ldc < plan->lmax)) return VECCHIA_EINVAL;
   ThetaPack thp;
   memset(&thp, 0, sizeof(thp));
-  if (!theta_to_dev(*theta, d, thp.t[0]))
-    return (theta->nu == 0.5 || theta->nu == 1.5 || theta->nu == 2.5) ? VECCHIA_EINVAL : VECCHIA_EUNSUPPORTED;
+  const int st = theta_status(*theta, d, thp.t[0]);
+  if (st) return st;
   hipStream_t s = (hipStream_t)stream;
   AdjArgs a;
   memset(&a, 0, sizeof(a));
@@ -746,6 +771,7 @@ extern "C" int vecchia_predict(const vecchia_plan* plan, const double* locs_obs,
   a.out_var = var;
   a.out_cov = cov;
   a.ldc = cov ? ldc : 0;
+  a.gen = thp.t[0].nu_code == 3;
   const int* sched = at<int>(plan->ws, plan->off_sched);
   const bool conc = plan->exec != nullptr;
   TimingRec span;

@@ -14,6 +14,7 @@ bool wave_fits(int g, bool fp32) { return g >= 1 && g <= (fp32 ? kWaveMaxG32 : k
 
 hipError_t launch_wave(int g, bool fp32, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
   if (!wave_fits(g, fp32)) return hipErrorInvalidValue;
+  if (a.gen) return fp32 ? launch_wave_gen_f32(g, mode, a, thp, grid, s) : launch_wave_gen_f64(g, mode, a, thp, grid, s);
   return fp32 ? launch_wave_f32(g, mode, a, thp, grid, s) : launch_wave_f64(g, mode, a, thp, grid, s);
 }
 

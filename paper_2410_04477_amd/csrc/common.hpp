@@ -18,13 +18,102 @@ struct ThetaDev {
   double nugget;
   double inv_scale[3];
   double inv_range;   // 1 / range (gradient w.r.t. range)
-  int nu_code;        // 0: nu = 1/2, 1: nu = 3/2, 2: nu = 5/2
-  int pad_;
+  int nu_code;        // 0: nu = 1/2, 1: nu = 3/2, 2: nu = 5/2, 3: any other nu (Bessel form)
+  int nu_n;           // nu_code 3: nu = nu_n + nu_mu, |nu_mu| <= 1/2
+  // nu_code 3, order-only constants of the Bessel evaluation (host-computed):
+  // Temme's Gamma1(mu), Gamma2(mu), 1/Gamma(1 + mu), 1/Gamma(1 - mu), and
+  // log(2^(1 - nu) / Gamma(nu))
+  double nu_mu, nu_gam1, nu_gam2, nu_gampl, nu_gammi, nu_lognorm;
 };
 
 struct ThetaPack {
   ThetaDev t[kMaxThetaPerLaunch];
 };
+
+// Matern correlation for any nu > 0, eq. (maternkernel) with the modified
+// Bessel function of the second kind: rho(x) = 2^(1-nu)/Gamma(nu) x^nu K_nu(x),
+// in FP64.  K is evaluated at order mu = nu - n (|mu| <= 1/2) by Temme's series
+// (Temme 1975) for x <= 2 or Steed's continued fraction CF2 (Thompson and
+// Barnett 1987) for x > 2, each giving K_mu and K_(mu+1), then raised to order
+// nu by the forward recurrence K_(k+1) = 2k/x K_k + K_(k-1), which is stable for
+// K.  Also returns g = 2^(1-nu)/Gamma(nu) x^(nu+1) K_(nu-1)(x), from
+// d/dx [x^nu K_nu(x)] = -x^nu K_(nu-1)(x): d rho(h/range) / d range = g / range.
+// Not inlined: its loops would otherwise be copied into every generation site.
+__device__ __noinline__ inline void matern_general(double x, double mu, double gam1, double gam2, double gampl,
+                                                   double gammi, double lognorm, int n, double* rho, double* g) {
+  if (!(x > 0.0)) {
+    *rho = 1.0;
+    *g = 0.0;
+    return;
+  }
+  const double kEps = 1e-16, kPi = 3.14159265358979323846;
+  double km, kp;   // K_mu(x), K_(mu+1)(x)
+  if (x <= 2.0) {
+    // Temme: K_mu = sum c_k f_k, K_(mu+1) = (2/x) sum c_k (p_k - k f_k), c_k = (x^2/4)^k / k!
+    const double lx = -log(0.5 * x);   // ln(2/x)
+    const double sg = mu * lx;
+    const double fact = fabs(mu) < 1e-14 ? 1.0 : kPi * mu / sin(kPi * mu);
+    const double fact2 = fabs(sg) < 1e-14 ? 1.0 : sinh(sg) / sg;
+    double f = fact * (gam1 * cosh(sg) + gam2 * fact2 * lx);
+    const double es = exp(sg);
+    double p = 0.5 * es / gampl;    // (x/2)^-mu Gamma(1 + mu) / 2
+    double q = 0.5 / (es * gammi);  // (x/2)^mu Gamma(1 - mu) / 2
+    const double x24 = 0.25 * x * x;
+    double c = 1.0, s0 = f, s1 = p;
+    for (int k = 1; k < 200; ++k) {
+      const double dk = (double)k;
+      f = (dk * f + p + q) / (dk * dk - mu * mu);
+      c *= x24 / dk;
+      p /= dk - mu;
+      q /= dk + mu;
+      const double t0 = c * f;
+      s0 += t0;
+      s1 += c * (p - dk * f);
+      if (fabs(t0) < kEps * fabs(s0)) break;
+    }
+    km = s0;
+    kp = s1 * (2.0 / x);
+  } else {
+    // Steed's algorithm for CF2: K_mu = sqrt(pi / 2x) e^-x / s
+    const double a1 = 0.25 - mu * mu;
+    double b = 2.0 * (1.0 + x), d = 1.0 / b, h = d, dh = d;
+    double q1 = 0.0, q2 = 1.0, q = a1, c = a1, a = -a1;
+    double s = 1.0 + q * dh;
+    for (int i = 2; i < 1000; ++i) {
+      a -= 2.0 * (i - 1);
+      c = -a * c / i;
+      const double qn = (q1 - b * q2) / a;
+      q1 = q2;
+      q2 = qn;
+      q += c * qn;
+      b += 2.0;
+      d = 1.0 / (b + a * d);
+      dh = (b * d - 1.0) * dh;
+      h += dh;
+      const double ds = q * dh;
+      s += ds;
+      if (fabs(ds) < kEps * fabs(s)) break;
+    }
+    km = sqrt(kPi / (2.0 * x)) * exp(-x) / s;
+    kp = km * (mu + x + 0.5 - a1 * h) / x;
+  }
+  double kn, kn1;   // K_nu, K_(nu-1)
+  if (n == 0) {
+    kn = km;
+    kn1 = kp - (2.0 * mu / x) * km;   // K_(mu-1)
+  } else {
+    for (int k = 1; k < n; ++k) {
+      const double t = (2.0 * (mu + k) / x) * kp + km;
+      km = kp;
+      kp = t;
+    }
+    kn = kp;
+    kn1 = km;
+  }
+  const double nu = mu + n, lxn = log(x);
+  *rho = exp(lognorm + nu * lxn) * kn;
+  *g = exp(lognorm + (nu + 1.0) * lxn) * kn1;
+}
 
 template <typename T> __device__ __forceinline__ T expneg(T x);
 template <> __device__ __forceinline__ double expneg<double>(double x) { return exp(-x); }
@@ -61,6 +150,28 @@ struct MaternCoef {
     const T e = expneg<T>(x);
     r = e * (T(1) + x * (c1 + c2 * x));
     dr = x * inv_range * e * (g0 + x * (g1 + g2 * x));
+  }
+};
+
+// The correlation a kernel generates: closed forms (GEN = false), or the
+// Bessel form for any nu (GEN = true; FP64 evaluation rounded to T).
+template <typename T, bool GEN> struct MaternF;
+template <typename T> struct MaternF<T, false> : MaternCoef<T> {
+  __device__ __forceinline__ explicit MaternF(const ThetaDev& t) : MaternCoef<T>(t.nu_code) {}
+};
+template <typename T> struct MaternF<T, true> {
+  const ThetaDev& t;
+  __device__ __forceinline__ explicit MaternF(const ThetaDev& th) : t(th) {}
+  __device__ __forceinline__ T rho(T x) const {
+    double r, g;
+    matern_general((double)x, t.nu_mu, t.nu_gam1, t.nu_gam2, t.nu_gampl, t.nu_gammi, t.nu_lognorm, t.nu_n, &r, &g);
+    return T(r);
+  }
+  __device__ __forceinline__ void rho_drange(T x, T inv_range, T& r, T& dr) const {
+    double rr, g;
+    matern_general((double)x, t.nu_mu, t.nu_gam1, t.nu_gam2, t.nu_gampl, t.nu_gammi, t.nu_lognorm, t.nu_n, &rr, &g);
+    r = T(rr);
+    dr = T(g) * inv_range;
   }
 };
 

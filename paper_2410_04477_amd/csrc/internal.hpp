@@ -57,6 +57,7 @@ struct AdjArgs {
   double* out_var;       // [new location]: conditional variance
   double* out_cov;       // [block][ldc][ldc]: conditional covariance, or null
   int ldc;
+  int gen;               // some theta of the launch has nu outside {1/2, 3/2, 5/2} (Bessel form)
 };
 
 hipError_t launch_adjoint(int cfg, bool fp32, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
@@ -84,6 +85,9 @@ inline bool wave_split(int g, bool fp32) { return fp32 && g >= 10; }
 __host__ __device__ constexpr int pred_rows(int m) { return (m + 3) & ~3; }
 hipError_t launch_wave_f32(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 hipError_t launch_wave_f64(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+hipError_t launch_wave_gen_f32(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+hipError_t launch_wave_gen_f64(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+// dispatches on a.gen to the closed-form or the Bessel-form kernels
 hipError_t launch_wave(int g, bool fp32, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 struct LargeArgs {
   const double* locs;

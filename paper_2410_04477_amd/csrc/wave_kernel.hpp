@@ -110,7 +110,8 @@ constexpr int wave_min_waves() { return sizeof(T) == 4 && (G <= 9 || MODE == 3) 
 // carries y_N and zeros, and only the neighbour columns are eliminated, which
 // leaves the Schur complement -- the conditional covariance of the block and,
 // in the border row, minus its conditional mean -- in the trailing tiles.
-template <typename T, int G, int MODE>
+// GEN: covariances by the Bessel form for any nu instead of the closed forms.
+template <typename T, int G, int MODE, bool GEN>
 __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
   constexpr int P = 16 * G;
   constexpr int NT = G * (G + 1) / 2;
@@ -171,7 +172,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   T* Lg = reinterpret_cast<T*>(a.tiles) + (size_t)(wi - a.item_base) * (NT * 256);   // tile slot (MODE 1-3)
   double acc_ll = 0.0;
   int flag = 0;
-  const MaternCoef<T> mc(th.nu_code);
+  const MaternF<T, GEN> mc(th);
   if constexpr (MODE != 3) {   // MODE 3 starts from the factor tiles of a MODE 2 launch
 
   // ---- generate the bordered joint matrix in the accumulator tiles ----------
@@ -640,45 +641,45 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   }
 }
 
-template <typename T, int G, int MODE>
+template <typename T, int G, int MODE, bool GEN>
 static hipError_t launch_wave_g(const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
   const size_t lds = sizeof(T) * (size_t)wave_lds_elems(G, MODE);
-  hipLaunchKernelGGL((bv_wave_kernel<T, G, MODE>), dim3(grid), dim3(64), lds, s, a, thp);
+  hipLaunchKernelGGL((bv_wave_kernel<T, G, MODE, GEN>), dim3(grid), dim3(64), lds, s, a, thp);
   return hipGetLastError();
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool GEN = false>
 static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
   if constexpr (MODE == 2 || MODE == 3) {   // split gradient: only the classes that use it
-    if (g == 10) return launch_wave_g<T, 10, MODE>(a, thp, grid, s);
-    if (g == 11) return launch_wave_g<T, 11, MODE>(a, thp, grid, s);
+    if (g == 10) return launch_wave_g<T, 10, MODE, GEN>(a, thp, grid, s);
+    if (g == 11) return launch_wave_g<T, 11, MODE, GEN>(a, thp, grid, s);
     return hipErrorInvalidValue;
   } else if constexpr (MODE == 1 && sizeof(T) == 4) {   // FP32 G >= 10 use the split gradient
     switch (g) {
-      case 1: return launch_wave_g<T, 1, MODE>(a, thp, grid, s);
-      case 2: return launch_wave_g<T, 2, MODE>(a, thp, grid, s);
-      case 3: return launch_wave_g<T, 3, MODE>(a, thp, grid, s);
-      case 4: return launch_wave_g<T, 4, MODE>(a, thp, grid, s);
-      case 5: return launch_wave_g<T, 5, MODE>(a, thp, grid, s);
-      case 6: return launch_wave_g<T, 6, MODE>(a, thp, grid, s);
-      case 7: return launch_wave_g<T, 7, MODE>(a, thp, grid, s);
-      case 8: return launch_wave_g<T, 8, MODE>(a, thp, grid, s);
-      case 9: return launch_wave_g<T, 9, MODE>(a, thp, grid, s);
+      case 1: return launch_wave_g<T, 1, MODE, GEN>(a, thp, grid, s);
+      case 2: return launch_wave_g<T, 2, MODE, GEN>(a, thp, grid, s);
+      case 3: return launch_wave_g<T, 3, MODE, GEN>(a, thp, grid, s);
+      case 4: return launch_wave_g<T, 4, MODE, GEN>(a, thp, grid, s);
+      case 5: return launch_wave_g<T, 5, MODE, GEN>(a, thp, grid, s);
+      case 6: return launch_wave_g<T, 6, MODE, GEN>(a, thp, grid, s);
+      case 7: return launch_wave_g<T, 7, MODE, GEN>(a, thp, grid, s);
+      case 8: return launch_wave_g<T, 8, MODE, GEN>(a, thp, grid, s);
+      case 9: return launch_wave_g<T, 9, MODE, GEN>(a, thp, grid, s);
       default: return hipErrorInvalidValue;
     }
   } else {
   switch (g) {
-    case 1: return launch_wave_g<T, 1, MODE>(a, thp, grid, s);
-    case 2: return launch_wave_g<T, 2, MODE>(a, thp, grid, s);
-    case 3: return launch_wave_g<T, 3, MODE>(a, thp, grid, s);
-    case 4: return launch_wave_g<T, 4, MODE>(a, thp, grid, s);
-    case 5: return launch_wave_g<T, 5, MODE>(a, thp, grid, s);
-    case 6: return launch_wave_g<T, 6, MODE>(a, thp, grid, s);
-    case 7: return launch_wave_g<T, 7, MODE>(a, thp, grid, s);
-    case 8: return launch_wave_g<T, 8, MODE>(a, thp, grid, s);
-    case 9: return launch_wave_g<T, 9, MODE>(a, thp, grid, s);
-    case 10: return launch_wave_g<T, 10, MODE>(a, thp, grid, s);
-    case 11: return launch_wave_g<T, 11, MODE>(a, thp, grid, s);
+    case 1: return launch_wave_g<T, 1, MODE, GEN>(a, thp, grid, s);
+    case 2: return launch_wave_g<T, 2, MODE, GEN>(a, thp, grid, s);
+    case 3: return launch_wave_g<T, 3, MODE, GEN>(a, thp, grid, s);
+    case 4: return launch_wave_g<T, 4, MODE, GEN>(a, thp, grid, s);
+    case 5: return launch_wave_g<T, 5, MODE, GEN>(a, thp, grid, s);
+    case 6: return launch_wave_g<T, 6, MODE, GEN>(a, thp, grid, s);
+    case 7: return launch_wave_g<T, 7, MODE, GEN>(a, thp, grid, s);
+    case 8: return launch_wave_g<T, 8, MODE, GEN>(a, thp, grid, s);
+    case 9: return launch_wave_g<T, 9, MODE, GEN>(a, thp, grid, s);
+    case 10: return launch_wave_g<T, 10, MODE, GEN>(a, thp, grid, s);
+    case 11: return launch_wave_g<T, 11, MODE, GEN>(a, thp, grid, s);
     default: return hipErrorInvalidValue;
   }
   }

@@ -49,8 +49,10 @@ def test_binding_signatures_cover_header():
 
 def test_fp32_wave_kernels_keep_their_tiles_in_registers():
     """The build records each kernel's register use (compiler resource remarks).
-    No FP32 one-wave kernel may spill (its tiles would go through scratch), and
-    the FP32 classes up to G = 9 must keep two waves per SIMD."""
+    No FP32 closed-form one-wave kernel may spill (its tiles would go through
+    scratch), and the FP32 classes up to G = 9 must keep two waves per SIMD.
+    (The Bessel-form kernels, for nu outside the closed forms, call a
+    non-inlined function and keep a call frame in scratch.)"""
     import json
     import re
     path = os.path.join(ROOT, "paper_2410_04477_amd", "_build", "kernel_resources.json")
@@ -59,7 +61,7 @@ def test_fp32_wave_kernels_keep_their_tiles_in_registers():
     res = json.load(open(path))
     seen = 0
     for name, r in res.items():
-        mt = re.search(r"bv_wave_kernelIfLi(\d+)ELi(\d)E", name)
+        mt = re.search(r"bv_wave_kernelIfLi(\d+)ELi(\d)ELb0E", name)
         if not mt:
             continue
         seen += 1

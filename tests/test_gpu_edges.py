@@ -35,7 +35,7 @@ def test_invalid_and_unsupported_theta_are_status_codes():
     good = (1.0, 0.1, 1e-3, 1.5)
     for bad, word in (((0.0, 0.1, 1e-3, 1.5), "invalid"), ((1.0, -0.1, 1e-3, 1.5), "invalid"),
                       ((1.0, 0.1, -1e-3, 1.5), "invalid"), ((float("nan"), 0.1, 1e-3, 1.5), "invalid"),
-                      ((1.0, 0.1, 1e-3, 1.0), "unsupported"), ((1.0, 0.1, 1e-3, 0.5, (1.0, 0.0, 1.0)), "invalid")):
+                      ((1.0, 0.1, 1e-3, 12.0), "unsupported"), ((1.0, 0.1, 1e-3, 0.5, (1.0, 0.0, 1.0)), "invalid")):
         with pytest.raises(VecchiaError, match=word):
             api.loglik(plan, lp, yp, nidx, [good, bad])
         with pytest.raises(VecchiaError, match=word):

@@ -1,0 +1,134 @@
+"""Matern covariance for any nu (Bessel form) on the GPU: the correlation
+itself over both branches of the Bessel evaluation, then log-likelihood,
+gradient and prediction against the numpy oracle (scipy's K_nu), and the
+error paths."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from cases import problem
+from oracle import loglik as OL, matern, predict as PR
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+NUS = [0.3, 0.8, 1.0, 2.0, 3.7]
+
+
+def _t(a, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device=DEV)
+
+
+@pytest.mark.parametrize("nu", [0.05, 0.3, 0.5001, 0.8, 1.0, 1.2, 2.0, 3.7, 7.5, 10.0])
+def test_correlation_through_one_neighbour_prediction(nu):
+    """One neighbour and one new point per block: the conditional mean is
+    sigma2 rho(x) / (sigma2 + nugget) y, so it returns rho at 400 distances
+    from 1e-4 to 60 range units (Temme's series below x = 2, the continued
+    fraction above), compared with 2^(1-nu)/Gamma(nu) x^nu K_nu(x) from scipy."""
+    from paper_2410_04477_amd import api
+    th = W.Theta(1.0, 1.0, 0.0, nu)
+    x = np.geomspace(1e-4, 60.0, 400)
+    s_obs = np.stack([np.zeros_like(x), np.zeros_like(x)], 1)
+    s_obs[:, 0] = np.arange(x.size) * 1e3   # far apart: each block sees only its own neighbour
+    s_new = s_obs.copy()
+    s_new[:, 1] = x
+    bp = np.arange(x.size + 1)
+    npt, nid = np.arange(x.size + 1), np.arange(x.size)
+    plan = api.Plan(_t(bp, torch.int32), _t(npt, torch.int32), x.size, 1, "mfma", predict=True)
+    mean, var, _ = api.predict(plan, _t(s_obs), _t(np.ones(x.size)), _t(s_new), _t(nid, torch.int32), th)
+    rho = mean.cpu().numpy()
+    ref = matern.rho_general(x, nu)
+    np.testing.assert_allclose(rho, ref, rtol=1e-12, atol=1e-300)
+    np.testing.assert_allclose(var.cpu().numpy(), 1.0 - ref * ref, rtol=1e-10, atol=1e-13)
+
+
+def _gpu_ll(pb, thetas, precision, grad=False):
+    from paper_2410_04477_amd import api
+    plan = api.Plan(_t(pb["block_ptr"], torch.int32), _t(pb["nbr_ptr"], torch.int32), pb["n"], len(thetas))
+    args = (plan, _t(pb["locs_perm"]), _t(pb["y_perm"]), _t(pb["nbr_idx"], torch.int32), thetas, precision)
+    if grad:
+        ll, g, cnt, part, gpart = api.loglik_grad(*args, want_partial=True)
+        return ll.cpu().numpy(), g.cpu().numpy(), part.cpu().numpy(), gpart.cpu().numpy(), plan
+    ll, cnt, part = api.loglik(*args, want_partial=True)
+    return ll.cpu().numpy(), None, part.cpu().numpy(), None, plan
+
+
+@pytest.mark.parametrize("m,bc", [(12, 80), (60, 80), (139, 150)])
+def test_loglik_matches_numpy_oracle(m, bc):
+    """FP64 per block within 1e-8 and the FP32-bulk total within 1e-4, for a
+    batch mixing Bessel-form and closed-form nu (the classes span G = 4 .. 11)."""
+    base = W.Theta(1.2, 0.08, 1e-3, 1.5)
+    pb = problem(f"gnu{m}", 1500, 2, bc, m, base, 71 + m)
+    thetas = [base.replace(nu=nu) for nu in NUS] + [base]
+    ll64, _, p64, _, plan = _gpu_ll(pb, thetas, "fp64")
+    ll32, _, _, _, _ = _gpu_ll(pb, thetas, "fp32")
+    print("classes G", sorted(int(c) + 1 for c in plan.c.bucket_cfg[:plan.c.nbuckets]))
+    args = (pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"])
+    for k, th in enumerate(thetas):
+        ref = OL.block_terms(*args, th)
+        np.testing.assert_allclose(p64[k], ref, rtol=1e-8, atol=1e-9)
+        assert abs(ll64[k] - ref.sum()) <= 1e-8 * abs(ref.sum())
+        e32 = abs(ll32[k] - ref.sum()) / abs(ref.sum())
+        print(f"nu={th.nu}: fp64 rel {abs(ll64[k] - ref.sum()) / abs(ref.sum()):.1e}, fp32-bulk rel {e32:.1e}")
+        assert e32 <= 1e-4, (th.nu, ll32[k], ref.sum())
+
+
+@pytest.mark.parametrize("nu", [0.8, 2.0])
+def test_gradient_matches_numpy_oracle(nu):
+    """FP64 adjoint within 1e-8 of the oracle's trace formula; FP32-bulk per
+    block within 1e-3 of the scale of its terms."""
+    th = W.Theta(1.2, 0.08, 1e-3, nu)
+    pb = problem("gnug", 1200, 2, 60, 100, W.Theta(1.2, 0.08, 1e-3, 1.5), 77)
+    args = (pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"])
+    ref = OL.grad_trace(*args, th)
+    _, g64, _, gp64, _ = _gpu_ll(pb, [th], "fp64", grad=True)
+    _, g32, _, gp32, _ = _gpu_ll(pb, [th], "fp32", grad=True)
+    assert np.linalg.norm(g64[0] - ref.sum(0)) <= 1e-8 * np.linalg.norm(ref.sum(0))
+    np.testing.assert_allclose(gp64[0], ref, rtol=1e-7, atol=1e-7 * np.abs(ref).max())
+    scale = np.abs(ref).sum(0)
+    assert np.all(np.abs(g32[0] - ref.sum(0)) <= 1e-3 * scale)
+
+
+def test_prediction_matches_oracle():
+    from paper_2410_04477_amd import api
+    th = W.Theta(1.1, 0.12, 2e-3, 1.3)
+    g = W.rng(181)
+    s_obs, s_new = g.random((800, 2)), g.random((90, 2))
+    y_obs = g.standard_normal(800)
+    bp = np.arange(0, 91, 9)
+    npt, nid = PR.pred_neighbors(s_obs, s_new, bp, [1.0, 1.0], 40)
+    mean_o, var_o, covs_o = PR.predict(s_obs, y_obs, s_new, bp, npt, nid, th)
+    plan = api.Plan(_t(bp, torch.int32), _t(npt, torch.int32), 90, 1, "mfma", predict=True)
+    mean, var, cov = api.predict(plan, _t(s_obs), _t(y_obs), _t(s_new), _t(nid, torch.int32), th, True)
+    assert np.max(np.abs(mean.cpu().numpy() - mean_o)) <= 1e-9
+    assert np.max(np.abs(var.cpu().numpy() - var_o)) <= 1e-10
+    cov = cov.cpu().numpy()
+    for i in range(bp.size - 1):
+        assert np.max(np.abs(cov[i, :9, :9] - covs_o[i])) <= 1e-10
+
+
+def test_error_paths():
+    from paper_2410_04477_amd import api
+    from paper_2410_04477_amd._lib import VecchiaError
+    th = W.Theta(1.0, 0.1, 1e-3, 1.5)
+    pb = problem("gnu-err", 400, 2, 40, 20, th, 91)
+    lp, yp, nid = _t(pb["locs_perm"]), _t(pb["y_perm"]), _t(pb["nbr_idx"], torch.int32)
+    bp, npt = _t(pb["block_ptr"], torch.int32), _t(pb["nbr_ptr"], torch.int32)
+    plan = api.Plan(bp, npt, 400, 1)
+    for nu, word in ((0.01, "unsupported"), (12.0, "unsupported"), (-1.0, "invalid"), (float("nan"), "invalid")):
+        with pytest.raises(VecchiaError, match=word):
+            api.loglik(plan, lp, yp, nid, [th.replace(nu=nu)])
+    # the Bessel form runs on the one-wave kernels only
+    tplan = api.Plan(bp, npt, 400, 1, "tiles")
+    with pytest.raises(VecchiaError, match="unsupported"):
+        api.loglik(tplan, lp, yp, nid, [th.replace(nu=1.0)])
+    big = problem("gnu-large", 1200, 2, 40, 190, th, 93)
+    lplan = api.Plan(_t(big["block_ptr"], torch.int32), _t(big["nbr_ptr"], torch.int32), 1200, 1)
+    assert lplan.c.nlarge > 0
+    with pytest.raises(VecchiaError, match="unsupported"):
+        api.loglik(lplan, _t(big["locs_perm"]), _t(big["y_perm"]), _t(big["nbr_idx"], torch.int32),
+                   [th.replace(nu=1.0)])
+    # closed forms still take their own path after a Bessel-form call
+    ll, _, _ = api.loglik(plan, lp, yp, nid, [th])
+    ref = OL.loglik(pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"], th)
+    assert abs(float(ll[0]) - ref) <= 1e-8 * abs(ref)

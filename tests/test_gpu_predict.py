@@ -155,7 +155,7 @@ def test_prediction_edge_cases():
     with pytest.raises(VecchiaError, match="invalid"):
         api.Plan(_t(bp, torch.int32), _t(npt, torch.int32), 7, 2, "mfma", predict=True)
     with pytest.raises(VecchiaError, match="unsupported"):
-        api.predict(plan, _t(s_obs), _t(y_obs), _t(s_new), _t(nid, torch.int32), (1.0, 0.1, 0.0, 1.0))
+        api.predict(plan, _t(s_obs), _t(y_obs), _t(s_new), _t(nid, torch.int32), (1.0, 0.1, 0.0, 12.0))
     lplan = api.Plan(_t(bp, torch.int32), _t(npt, torch.int32), 7, 1, "mfma")
     with pytest.raises(VecchiaError, match="invalid"):
         api.predict(lplan, _t(s_obs), _t(y_obs), _t(s_new), _t(nid, torch.int32), th)
