@@ -210,6 +210,17 @@ def main() -> int:
         variants["speedup_fp32_over_fp64_loglik_grad"] = evals / variants["fp64_loglik_grad_evals_per_s"]
         variants["speedup_fp32_over_fp64_loglik"] = (variants["fp32_loglik_evals_per_s"]
                                                      / variants["fp64_loglik_evals_per_s"])
+        # an order outside the closed forms (Bessel-form kernels), same workload
+        log("timing fp32 loglik+grad at nu = 1.0 (Bessel form)")
+        th_g = [(t[0], t[1], t[2], 1.0, t[4]) for t in thetas]
+        for th in th_g[:1]:
+            model.loglik_grad([th], "fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k2):
+            model.loglik_grad([th_g[i % len(th_g)]], "fp32")
+        torch.cuda.synchronize()
+        variants["fp32_loglik_grad_nu1.0_bessel_evals_per_s"] = k2 / (time.perf_counter() - t0)
     tt = [thetas[0]]
     l64, g64, _, _, gp64 = model.loglik_grad(tt, "fp64", want_partial=True)
     l32, g32, c32, _, _ = model.loglik_grad(tt, "fp32")

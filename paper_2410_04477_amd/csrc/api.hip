@@ -108,6 +108,7 @@ struct Exec {
   hipStream_t side[kSideStreams] = {};
   hipEvent_t fork = nullptr;
   hipEvent_t join[kSideStreams] = {};
+  hipEvent_t mark = nullptr;   // end of a split class's first factorisation launch
 };
 }  // namespace
 
@@ -268,6 +269,7 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
     Exec* ex = new Exec();
     plan->exec = ex;
     VCHECK_HIP(hipEventCreateWithFlags(&ex->fork, hipEventDisableTiming));
+    VCHECK_HIP(hipEventCreateWithFlags(&ex->mark, hipEventDisableTiming));
     for (int k = 0; k < kSideStreams; ++k) {
       VCHECK_HIP(hipStreamCreateWithFlags(&ex->side[k], hipStreamNonBlocking));
       VCHECK_HIP(hipEventCreateWithFlags(&ex->join[k], hipEventDisableTiming));
@@ -305,7 +307,8 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 // 1: value + gradient.  VECCHIA_EUNSUPPORTED when the four-wave adjoint's
 // right-hand sides do not fit the device LDS.
 static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mode, AdjArgs a, const ThetaPack& thp,
-                             int grid, hipStream_t s, void* tiles, size_t tile_bytes, hipStream_t s2 = nullptr) {
+                             int grid, hipStream_t s, void* tiles, size_t tile_bytes, hipStream_t s2 = nullptr,
+                             hipEvent_t mark = nullptr) {
   const int g = plan->bucket_cfg[q] + 1;
   a.gen = 0;
   for (int t = 0; t < a.ntheta; ++t) a.gen |= thp.t[t].nu_code == 3;
@@ -331,6 +334,7 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
         const int n = grid - k * h < h ? grid - k * h : h;
         const hipStream_t sk = (k & 1) ? s2 : s;
         VCHECK_HIP(launch_wave(g, fp32, 2, a, thp, n, sk));
+        if (k == 0 && mark) VCHECK_HIP(hipEventRecord(mark, sk));
         VCHECK_HIP(launch_wave(g, fp32, 3, a, thp, n, sk));
       }
       return VECCHIA_OK;
@@ -446,6 +450,7 @@ extern "C" int vecchia_plan_destroy(vecchia_plan* plan) {
       if (ex->join[k]) hipEventDestroy(ex->join[k]);
     }
     if (ex->fork) hipEventDestroy(ex->fork);
+    if (ex->mark) hipEventDestroy(ex->mark);
     delete ex;
     plan->exec = nullptr;
   }
@@ -683,6 +688,16 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
       off[q + 1] = off[q] + (wave ? ns * nt * wave_tile_bytes(g, fp32) : 0);
     }
     const bool conc = plan->exec != nullptr && off[plan->nbuckets] <= plan->aux_ws_bytes;
+    // the largest class waits for the first factorisation launch of the split
+    // (two-launch) class with the most blocks, so that the long one-wave-per-SIMD
+    // factorisation items start first and the fine-grained class fills in last
+    int qmark = -1;
+    if (conc && plan->engine == kEngineMfma)
+      for (int q = 0; q < plan->nbuckets; ++q)
+        if (q != plan->bucket_main && wave_split(plan->bucket_cfg[q] + 1, fp32) &&
+            (qmark < 0 || plan->bucket_off[q + 1] - plan->bucket_off[q] >
+                              plan->bucket_off[qmark + 1] - plan->bucket_off[qmark]))
+          qmark = q;
     TimingRec span;
     VCHECK_HIP(time_begin(plan, plan->nbuckets, s, span));
     if (conc) VCHECK_HIP(fork_streams(plan, s));
@@ -697,10 +712,13 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
       VCHECK_HIP(time_begin(plan, q, sq, tr));
       if (plan->engine == kEngineTiles)
         VCHECK_ST(launch_tiles_adjoint(plan, q, fp32, a, thp, ns * nt, sq));
-      else if (conc)
+      else if (conc) {
+        Exec* ex = static_cast<Exec*>(plan->exec);
+        if (q == plan->bucket_main && qmark >= 0) VCHECK_HIP(hipStreamWaitEvent(sq, ex->mark, 0));
         VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq,
                                     static_cast<char*>(plan->aux_ws) + off[q], off[q + 1] - off[q],
-                                    spare_stream(plan, q)));
+                                    spare_stream(plan, q), q == qmark ? ex->mark : nullptr));
+      }
       else
         VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq, plan->aux_ws, plan->aux_ws_bytes));
       VCHECK_HIP(time_end(plan, sq, tr));
