@@ -86,6 +86,8 @@ reduce_partials_kernel(const double* __restrict__ partial, const int* __restrict
   const int* ff = flag + (size_t)tt * bc;
   double acc = 0.0;
   int nref = 0, nbad = 0;
+  // unrolled so that several loads are in flight; the additions keep their order
+#pragma unroll 8
   for (int i = threadIdx.x; i < bc; i += 256) {
     acc += pp[i];
     const int f = ff[i];
@@ -121,6 +123,7 @@ reduce_vec_kernel(const double* __restrict__ vec, int bc, int k, double* __restr
   const int c = blockIdx.x - tt * k;
   const double* pp = vec + (size_t)tt * bc * k;
   double acc = 0.0;
+#pragma unroll 8
   for (int i = threadIdx.x; i < bc; i += 256) acc += pp[(size_t)i * k + c];
   ssum[threadIdx.x] = acc;
   __syncthreads();

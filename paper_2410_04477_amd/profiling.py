@@ -8,7 +8,7 @@ calibrate the counters: bytes = counter * (known copy bytes / copy reading).
 
     python -m paper_2410_04477_amd.profiling kernels <kernel_trace.csv> --title T --command C
     python -m paper_2410_04477_amd.profiling traffic <fetch.csv> <write.csv> --kernel REGEX \
-        --copy-bytes B --sha S --out profiles/hbm_traffic.json
+        --name NAME --copy-bytes B --sha S [--calls REGEX] --out profiles/hbm_traffic.json
 """
 from __future__ import annotations
 
@@ -84,10 +84,12 @@ def concurrent_spans(trace_csv: str, kernel_regex: str):
     return [b - a for a, b in spans], counts
 
 
-def counter_per_dispatch(pmc_csv: str, counter: str, kernel_regex: str):
+def counter_per_dispatch(pmc_csv: str, counter: str, kernel_regex: str, calls_regex: str = ""):
     """Mean and count of one counter over the dispatches whose kernel name
     matches ``kernel_regex`` (values summed over the counter's instances per
-    dispatch)."""
+    dispatch).  With ``calls_regex`` the sum over those dispatches is divided
+    by the number of dispatches matching it instead (a call that launches a
+    size class in several pieces)."""
     header, rows = _rows(pmc_csv)
     iname = _col(header, "kernel_name")
     idisp = _col(header, "dispatch_id", "correlation_id")
@@ -99,16 +101,22 @@ def counter_per_dispatch(pmc_csv: str, counter: str, kernel_regex: str):
         if row[icn] == counter and pat.search(row[iname]):
             per[row[idisp]] += float(row[icv])
     vals = list(per.values())
+    if calls_regex:
+        cpat = re.compile(calls_regex)
+        ncalls = len({row[idisp] for row in rows if row[icn] == counter and cpat.search(row[iname])})
+        return (sum(vals) / ncalls if ncalls else float("nan")), len(vals)
     return (sum(vals) / len(vals) if vals else float("nan")), len(vals)
 
 
 COPY_REGEX = r"elementwise|copy|Copy"
 
 
-def traffic(fetch_csv: str, write_csv: str, kernel_regex: str, copy_bytes: float, copy_regex: str = COPY_REGEX):
-    """HBM bytes per launch of the matched kernel, counters calibrated on the copy."""
-    f_k, nf = counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel_regex)
-    w_k, nw = counter_per_dispatch(write_csv, "WRITE_SIZE", kernel_regex)
+def traffic(fetch_csv: str, write_csv: str, kernel_regex: str, copy_bytes: float, copy_regex: str = COPY_REGEX,
+            calls_regex: str = ""):
+    """HBM bytes per launch of the matched kernel (per call, with
+    ``calls_regex``), counters calibrated on the copy."""
+    f_k, nf = counter_per_dispatch(fetch_csv, "FETCH_SIZE", kernel_regex, calls_regex)
+    w_k, nw = counter_per_dispatch(write_csv, "WRITE_SIZE", kernel_regex, calls_regex)
     # the calibration copy is the largest dispatch of a copy kernel in each run
     def largest(path, counter):
         header, rows = _rows(path)
@@ -145,6 +153,7 @@ def main(argv=None) -> int:
     t.add_argument("--kernel", required=True, help="regex of the kernel name")
     t.add_argument("--name", required=True, help="key under which the result is stored")
     t.add_argument("--copy-bytes", type=float, required=True)
+    t.add_argument("--calls", default="", help="regex of one dispatch per call: report bytes per call")
     t.add_argument("--sha", required=True)
     t.add_argument("--command", default="")
     t.add_argument("--out", required=True)
@@ -160,7 +169,7 @@ def main(argv=None) -> int:
                                  f"{sum(sel) / len(sel) / 1e3:.1f} us, min {min(sel) / 1e3:.1f} us, "
                                  f"max {max(sel) / 1e3:.1f} us.\n")
         return 0
-    res = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes)
+    res = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, calls_regex=a.calls)
     try:
         with open(a.out) as fh:
             doc = json.load(fh)
