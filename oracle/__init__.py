@@ -15,6 +15,7 @@ Contents (each function cites the passage of the paper it follows):
   coracle     - the same Alg. 1 chain and gradient in plain C with OpenMP over
                 blocks (csrc/bv_oracle.c), for the larger workloads
   simulate    - exact-GP and sequential-Vecchia data simulators
+  ordering    - Morton and maxmin block orderings (Section 2.1)
   learned     - binned empirical variogram and an FP64 MLP forward/backward
   predict     - block Vecchia prediction (Alg. 2) and univariate conditional
                 simulation with PICP / MSPE

@@ -1,0 +1,74 @@
+"""Block orderings (Section 2.1: Morton and maxmin reorderings of the blocks),
+numpy FP64.  The KL divergence used to compare them (eq.
+(kl-gaussian-vecchia)) is loglik.kl_divergence.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Readings where the paper is silent:
+  * Blocks are ordered by their centroids (the mean of the block's metric-
+    scaled points, as for the neighbour search).
+  * Morton: each centroid coordinate is mapped to an integer cell on a grid of
+    2^B cells per axis over the centroids' bounding box (B = 32 in 2-D, 21 in
+    3-D, 63 bits in 1-D), cell = min(floor((c - lo) / (hi - lo) * 2^B), 2^B - 1);
+    the key interleaves the bits, axis 0 in the lowest position; blocks are
+    sorted by key, ties by block index.
+  * Maxmin: the first block is the one whose centroid is nearest the mean of
+    the centroids; each next block maximises the minimum squared distance to
+    the blocks already placed; ties by lowest block index.  Squared distances
+    are summed over the axes left to right without fused multiply-add.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from .preprocess import _sqdist, block_centroids
+
+
+def morton_keys(cen: np.ndarray) -> np.ndarray:
+    """64-bit interleaved cell indices of the points (rows of cen)."""
+    n, d = cen.shape
+    bits = {1: 63, 2: 32, 3: 21}[d]
+    lo, hi = cen.min(0), cen.max(0)
+    ext = np.where(hi > lo, hi - lo, 1.0)
+    scale = float(1 << bits)
+    cells = np.minimum(np.floor((cen - lo) / ext * scale), scale - 1).astype(np.uint64)
+    keys = np.zeros(n, dtype=np.uint64)
+    for b in range(bits):
+        for k in range(d):
+            keys |= ((cells[:, k] >> np.uint64(b)) & np.uint64(1)) << np.uint64(b * d + k)
+    return keys
+
+
+def morton_order(cen: np.ndarray) -> np.ndarray:
+    keys = morton_keys(cen)
+    return np.lexsort((np.arange(cen.shape[0]), keys))
+
+
+def maxmin_order(cen: np.ndarray) -> np.ndarray:
+    n = cen.shape[0]
+    mean = cen.sum(0) / n
+    first = int(np.lexsort((np.arange(n), _sqdist(mean, cen)))[0])
+    order = [first]
+    mind = _sqdist(cen[first], cen)
+    placed = np.zeros(n, dtype=bool)
+    placed[first] = True
+    for _ in range(n - 1):
+        cand = np.where(placed, -1.0, mind)
+        nxt = int(np.argmax(cand))          # first index of the maximum
+        order.append(nxt)
+        placed[nxt] = True
+        mind = np.minimum(mind, _sqdist(cen[nxt], cen))
+    return np.array(order, dtype=np.int64)
+
+
+def reorder(locs_perm: np.ndarray, block_ptr: np.ndarray, metric_scale, method: str):
+    """New block order of blocks already in some order: returns (order, point
+    permutation into locs_perm, new block_ptr)."""
+    cen = block_centroids(locs_perm, block_ptr, metric_scale)
+    order = {"morton": morton_order, "maxmin": maxmin_order}[method](cen)
+    sizes = np.diff(block_ptr)[order]
+    bp = np.zeros(order.size + 1, dtype=np.int64)
+    np.cumsum(sizes, out=bp[1:])
+    perm = np.concatenate([np.arange(block_ptr[b], block_ptr[b + 1]) for b in order]).astype(np.int64)
+    return order, perm, bp
+
