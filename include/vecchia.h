@@ -128,6 +128,33 @@ int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const doubl
                       int32_t* nbr_ptr, int32_t* nbr_idx, int64_t nbr_cap,
                       void* workspace, size_t ws_bytes, void* stream);
 
+/* Block orderings (Section 2.1): instead of the random order of
+ * vecchia_blocks, order the blocks by their centroids (mean of the block's
+ * metric-scaled points).
+ *   VECCHIA_ORDER_MORTON  Z order: each centroid coordinate to a cell of a 2^B
+ *                         grid over the centroids' bounding box (B = 63, 32,
+ *                         21 for d = 1, 2, 3), bits interleaved with axis 0
+ *                         lowest, sorted by key then block index
+ *   VECCHIA_ORDER_MAXMIN  first the block nearest the mean centroid (summed in
+ *                         block order), then each next block maximises the
+ *                         minimum squared distance to the blocks placed (ties:
+ *                         lowest index); one workgroup, O(bc^2) work
+ * vecchia_reorder_blocks takes points already grouped into blocks (locs_perm,
+ * block_ptr) and returns
+ *   block_order    out, bc int64: position -> current block index
+ *   point_perm     out, n int64: new point order as indices into locs_perm
+ *   block_ptr_out  out, bc+1 int32 for the new order
+ * Apply point_perm with vecchia_permute, then search neighbours.
+ *   workspace  >= vecchia_reorder_blocks_workspace_size(n, bc, d) bytes
+ * Synchronises `stream` (Morton: the bounding box goes through the host). */
+#define VECCHIA_ORDER_MORTON 1
+#define VECCHIA_ORDER_MAXMIN 2
+size_t vecchia_reorder_blocks_workspace_size(int64_t n, int64_t bc, int32_t d);
+int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_t d, const double* metric_scale,
+                           const int32_t* block_ptr, int64_t bc, int32_t method, int64_t* block_order,
+                           int64_t* point_perm, int32_t* block_ptr_out, void* workspace, size_t ws_bytes,
+                           void* stream);
+
 /* Kernel families.
  * VECCHIA_ENGINE_MFMA (default): each block's bordered joint matrix lives in
  *   16 x 16 matrix-core accumulator tiles of ONE wave (a 64-thread workgroup).

@@ -13,7 +13,7 @@ Readings where the paper is silent:
     the key interleaves the bits, axis 0 in the lowest position; blocks are
     sorted by key, ties by block index.
   * Maxmin: the first block is the one whose centroid is nearest the mean of
-    the centroids; each next block maximises the minimum squared distance to
+    the centroids (summed in block order); each next block maximises the minimum squared distance to
     the blocks already placed; ties by lowest block index.  Squared distances
     are summed over the axes left to right without fused multiply-add.
 """
@@ -46,7 +46,10 @@ def morton_order(cen: np.ndarray) -> np.ndarray:
 
 def maxmin_order(cen: np.ndarray) -> np.ndarray:
     n = cen.shape[0]
-    mean = cen.sum(0) / n
+    acc = np.zeros(cen.shape[1])
+    for i in range(n):            # summed in order, like the centroids themselves
+        acc = acc + cen[i]
+    mean = acc / n
     first = int(np.lexsort((np.arange(n), _sqdist(mean, cen)))[0])
     order = [first]
     mind = _sqdist(cen[first], cen)

@@ -13,6 +13,7 @@ MAX_BUCKETS = 24
 MAX_JOINT = 175
 ENGINE_MFMA, ENGINE_TILES, ENGINE_MFMA_WG = 0, 1, 2
 PLAN_PREDICT = 16
+ORDER_MORTON, ORDER_MAXMIN = 1, 2
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, FP32_BULK = 0, 1
@@ -75,6 +76,8 @@ SIGNATURES = {
     "vecchia_pred_neighbors_workspace_size": (SZ, [I64, I64, I64, I32, I32]),
     "vecchia_pred_neighbors": (ctypes.c_int, [P, I64, P, I64, I32, P, P, I64, I32, P, P, I64, P, SZ, P]),
     "vecchia_predict": (ctypes.c_int, [P, P, P, P, I32, P, P, P, P, P, P, P, I32, P]),
+    "vecchia_reorder_blocks_workspace_size": (SZ, [I64, I64, I32]),
+    "vecchia_reorder_blocks": (ctypes.c_int, [P, I64, I32, P, P, I64, I32, P, P, P, P, SZ, P]),
     "vecchia_condsim_workspace_size": (SZ, [I64]),
     "vecchia_condsim": (ctypes.c_int, [P, P, I64, P, I32, P, P, P, P, P, P, P, SZ, P]),
 }

@@ -108,6 +108,28 @@ def neighbors(locs_perm: torch.Tensor, block_ptr: torch.Tensor, m: int,
     return nptr, nidx[:total].clone()
 
 
+ORDERS = {"morton": L.ORDER_MORTON, "maxmin": L.ORDER_MAXMIN}
+
+
+def reorder_blocks(locs_perm: torch.Tensor, block_ptr: torch.Tensor, method: str,
+                   metric_scale: Optional[Sequence[float]] = None):
+    """Morton or maxmin order of the blocks by their centroids.  Returns
+    (block_order int64[bc], point_perm int64[n] into locs_perm, block_ptr int32[bc+1])."""
+    _dev_check(locs_perm, block_ptr)
+    n, d = locs_perm.shape
+    bc = block_ptr.numel() - 1
+    lib = L.lib()
+    dev = locs_perm.device
+    ws = torch.empty(max(1, int(lib.vecchia_reorder_blocks_workspace_size(n, bc, d))), dtype=torch.uint8, device=dev)
+    order = torch.empty(bc, dtype=torch.int64, device=dev)
+    perm = torch.empty(n, dtype=torch.int64, device=dev)
+    bp = torch.empty(bc + 1, dtype=torch.int32, device=dev)
+    ms = (ctypes.c_double * d)(*metric_scale) if metric_scale is not None else None
+    L.check(lib.vecchia_reorder_blocks(_p(locs_perm), n, d, ms, _p(block_ptr), bc, ORDERS[method], _p(order),
+                                       _p(perm), _p(bp), _p(ws), ws.numel(), _stream(dev)), "vecchia_reorder_blocks")
+    return order, perm, bp
+
+
 class Plan:
     """Launch schedule for one block / neighbour structure (vecchia_plan_init)."""
 

@@ -901,3 +901,215 @@ extern "C" int vecchia_pred_neighbors(const double* locs_obs, int64_t n_obs, con
   return neighbors_impl(cat, n_obs + n_new, d, w, bp, hb, bc, m, (int)n_obs, nbr_ptr, nbr_idx, nbr_cap,
                         at<void>(workspace, L.nbr), ws_bytes - L.nbr, s);
 }
+
+// ------------------------------------------------------------ block order --
+// Morton and maxmin orderings of the blocks (Section 2.1) by their centroids.
+
+namespace bv {
+
+__global__ void centroids_kernel(const double* __restrict__ locs, int d, double w0, double w1, double w2,
+                                 const int* __restrict__ block_ptr, int bc, double* __restrict__ cen) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= bc) return;
+  const double w[3] = {w0, w1, w2};
+  double c[3];
+  block_centroid(locs, d, w, block_ptr[b], block_ptr[b + 1], c);
+  for (int k = 0; k < d; ++k) cen[(size_t)b * d + k] = c[k];
+}
+
+// Interleaved cell bits (axis 0 lowest) on a 2^B grid over the bounding box.
+__global__ void morton_kernel(const double* __restrict__ cen, int bc, int d, double lo0, double lo1, double lo2,
+                              double ex0, double ex1, double ex2, unsigned long long* __restrict__ key,
+                              int64_t* __restrict__ idx) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= bc) return;
+  const int bits = d == 1 ? 63 : (d == 2 ? 32 : 21);
+  const double scale = (double)(1ull << bits);
+  const double lo[3] = {lo0, lo1, lo2}, ex[3] = {ex0, ex1, ex2};
+  unsigned long long cell[3] = {0, 0, 0};
+  for (int k = 0; k < d; ++k) {
+    const double t = floor((cen[(size_t)b * d + k] - lo[k]) / ex[k] * scale);
+    cell[k] = (unsigned long long)fmin(t, scale - 1.0);
+  }
+  unsigned long long v = 0;
+  for (int i = 0; i < bits; ++i)
+    for (int k = 0; k < d; ++k) v |= ((cell[k] >> i) & 1ull) << (i * d + k);
+  key[b] = v;
+  idx[b] = b;
+}
+
+// Greedy maxmin by one workgroup: the first block is the one nearest the mean
+// centroid; each next one maximises the minimum squared distance to the
+// blocks placed (ties: lowest index).  mind < 0 marks placed blocks.
+constexpr int kMaxminThreads = 1024;
+__global__ void __launch_bounds__(kMaxminThreads)
+maxmin_kernel(const double* __restrict__ cen, int bc, int d, double* __restrict__ mind, int64_t* __restrict__ order) {
+#pragma clang fp contract(off)
+  __shared__ double sv[kMaxminThreads];
+  __shared__ int si[kMaxminThreads];
+  __shared__ double sc[3];
+  const double one[3] = {1.0, 1.0, 1.0};
+  const int t = threadIdx.x;
+  if (t == 0) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int b = 0; b < bc; ++b)
+      for (int k = 0; k < d; ++k) acc[k] = acc[k] + cen[(size_t)b * d + k];
+    for (int k = 0; k < 3; ++k) sc[k] = k < d ? acc[k] / (double)bc : 0.0;
+  }
+  __syncthreads();
+  // pick = argmin (first) or argmax (later) of a per-block value, ties to the lowest index
+  auto reduce_pick = [&](double v, int i, bool want_max) {
+    sv[t] = v;
+    si[t] = i;
+    __syncthreads();
+    for (int s = kMaxminThreads / 2; s > 0; s >>= 1) {
+      if (t < s) {
+        const double a = sv[t], b = sv[t + s];
+        const int ia = si[t], ib = si[t + s];
+        const bool take = ib >= 0 && (ia < 0 || (want_max ? (b > a || (b == a && ib < ia)) : (b < a || (b == a && ib < ia))));
+        if (take) {
+          sv[t] = b;
+          si[t] = ib;
+        }
+      }
+      __syncthreads();
+    }
+    const int r = si[0];
+    __syncthreads();
+    return r;
+  };
+  double bv0 = INFINITY;
+  int bi = -1;
+  {
+    const double c[3] = {sc[0], sc[1], sc[2]};
+    for (int j = t; j < bc; j += kMaxminThreads) {
+      const double v = sqdist_fixed(c, cen, j, d, one);
+      if (bi < 0 || v < bv0) {
+        bv0 = v;
+        bi = j;
+      }
+    }
+  }
+  int cur = reduce_pick(bv0, bi, false);
+  for (int step = 0; step < bc; ++step) {
+    if (t == 0) order[step] = cur;
+    if (step == bc - 1) break;
+    const double c[3] = {cen[(size_t)cur * d], d > 1 ? cen[(size_t)cur * d + 1] : 0.0, d > 2 ? cen[(size_t)cur * d + 2] : 0.0};
+    double best = -1.0;
+    int besti = -1;
+    for (int j = t; j < bc; j += kMaxminThreads) {
+      double m;
+      if (j == cur) {
+        m = -1.0;
+      } else {
+        const double dj = sqdist_fixed(c, cen, j, d, one);
+        const double old = mind[j];
+        m = step == 0 ? dj : (old < 0.0 ? old : fmin(old, dj));
+      }
+      mind[j] = m;
+      if (m >= 0.0 && (besti < 0 || m > best)) {
+        best = m;
+        besti = j;
+      }
+    }
+    cur = reduce_pick(best, besti, true);
+  }
+}
+
+__global__ void block_sizes_kernel(const int* __restrict__ block_ptr, const int64_t* __restrict__ order, int bc,
+                                   int* __restrict__ sizes) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < bc) sizes[i] = block_ptr[order[i] + 1] - block_ptr[order[i]];
+  if (i == bc) sizes[i] = 0;
+}
+
+__global__ void gather_blocks_kernel(const int* __restrict__ block_ptr, const int64_t* __restrict__ order,
+                                     const int* __restrict__ new_ptr, int64_t* __restrict__ perm) {
+  const int i = blockIdx.x;
+  const int b0 = block_ptr[order[i]], l = block_ptr[order[i] + 1] - b0, o = new_ptr[i];
+  for (int j = threadIdx.x; j < l; j += blockDim.x) perm[o + j] = b0 + j;
+}
+
+}  // namespace bv
+
+namespace {
+struct OrderLayout {
+  size_t cen, key, key2, idx, idx2, mind, sizes, part, sort, scan, total;
+};
+OrderLayout order_layout(int64_t bc, int d) {
+  OrderLayout L;
+  size_t o = 0;
+  L.cen = o;   o = al256(o + sizeof(double) * (size_t)bc * d);
+  L.key = o;   o = al256(o + sizeof(unsigned long long) * (size_t)bc);
+  L.key2 = o;  o = al256(o + sizeof(unsigned long long) * (size_t)bc);
+  L.idx = o;   o = al256(o + sizeof(int64_t) * (size_t)bc);
+  L.idx2 = o;  o = al256(o + sizeof(int64_t) * (size_t)bc);
+  L.mind = o;  o = al256(o + sizeof(double) * (size_t)bc);
+  L.sizes = o; o = al256(o + sizeof(int) * (size_t)(bc + 1));
+  L.part = o;  o = al256(o + sizeof(double) * 6 * 1024);
+  size_t st = 0, sc = 0;
+  hipcub::DeviceRadixSort::SortPairs((void*)nullptr, st, (const unsigned long long*)nullptr,
+                                     (unsigned long long*)nullptr, (const int64_t*)nullptr, (int64_t*)nullptr,
+                                     (int)bc, 0, 64, (hipStream_t)0);
+  hipcub::DeviceScan::ExclusiveSum((void*)nullptr, sc, (const int*)nullptr, (int*)nullptr, (int)(bc + 1),
+                                   (hipStream_t)0);
+  L.sort = o;  o = al256(o + st);
+  L.scan = o;  o = al256(o + sc);
+  L.total = o;
+  return L;
+}
+}  // namespace
+
+extern "C" size_t vecchia_reorder_blocks_workspace_size(int64_t n, int64_t bc, int32_t d) {
+  (void)n;
+  if (bc <= 0 || d < 1 || d > 3) return 0;
+  return order_layout(bc, d).total;
+}
+
+extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_t d, const double* metric_scale,
+                                      const int32_t* block_ptr, int64_t bc, int32_t method, int64_t* block_order,
+                                      int64_t* point_perm, int32_t* block_ptr_out, void* workspace, size_t ws_bytes,
+                                      void* stream) {
+  if (!locs_perm || !block_ptr || !block_order || !point_perm || !block_ptr_out || !workspace) return VECCHIA_EINVAL;
+  if (n <= 0 || bc <= 0 || bc > n || d < 1 || d > 3 || n >= ((int64_t)1 << 31)) return VECCHIA_EINVAL;
+  if (method != VECCHIA_ORDER_MORTON && method != VECCHIA_ORDER_MAXMIN) return VECCHIA_EINVAL;
+  double w[3];
+  if (metric_weights(metric_scale, d, w)) return VECCHIA_EINVAL;
+  const OrderLayout L = order_layout(bc, d);
+  if (ws_bytes < L.total) return VECCHIA_ENOMEM;
+  hipStream_t s = (hipStream_t)stream;
+  double* cen = at<double>(workspace, L.cen);
+  const int ib = (int)bc;
+  hipLaunchKernelGGL(centroids_kernel, dim3(cdiv64(bc, 256)), dim3(256), 0, s, locs_perm, d, w[0], w[1], w[2],
+                     block_ptr, ib, cen);
+  PCHECK(hipGetLastError());
+  int64_t* order = block_order;
+  if (method == VECCHIA_ORDER_MORTON) {
+    const double one[3] = {1.0, 1.0, 1.0};
+    double lo[3], hi[3], ex[3];
+    int st = bbox(cen, bc, d, one, at<double>(workspace, L.part), lo, hi, s);
+    if (st) return st;
+    for (int k = 0; k < 3; ++k) ex[k] = (k < d && hi[k] > lo[k]) ? hi[k] - lo[k] : 1.0;
+    unsigned long long* key = at<unsigned long long>(workspace, L.key);
+    int64_t* idx = at<int64_t>(workspace, L.idx);
+    hipLaunchKernelGGL(morton_kernel, dim3(cdiv64(bc, 256)), dim3(256), 0, s, cen, ib, d, lo[0], lo[1], lo[2], ex[0],
+                       ex[1], ex[2], key, idx);
+    PCHECK(hipGetLastError());
+    size_t tmp = L.scan - L.sort;
+    // radix sort is stable: equal keys keep the ascending block index
+    PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key,
+                                              at<unsigned long long>(workspace, L.key2), idx, order, ib, 0, 64, s));
+  } else {
+    hipLaunchKernelGGL(maxmin_kernel, dim3(1), dim3(kMaxminThreads), 0, s, cen, ib, d,
+                       at<double>(workspace, L.mind), order);
+    PCHECK(hipGetLastError());
+  }
+  int* sizes = at<int>(workspace, L.sizes);
+  hipLaunchKernelGGL(block_sizes_kernel, dim3(cdiv64(bc + 1, 256)), dim3(256), 0, s, block_ptr, order, ib, sizes);
+  PCHECK(hipGetLastError());
+  size_t stmp = L.total - L.scan;
+  PCHECK(hipcub::DeviceScan::ExclusiveSum(at<void>(workspace, L.scan), stmp, sizes, block_ptr_out, ib + 1, s));
+  hipLaunchKernelGGL(gather_blocks_kernel, dim3(ib), dim3(64), 0, s, block_ptr, order, block_ptr_out, point_perm);
+  PCHECK(hipGetLastError());
+  return VECCHIA_OK;
+}

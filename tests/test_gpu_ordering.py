@@ -1,0 +1,81 @@
+"""Block orderings on the GPU (Morton, maxmin) against the oracle bit for
+bit, and the ordering study of Section 3 in small: KL divergences (eq.
+(kl-gaussian-vecchia)) of random, Morton and maxmin orders, GPU against the
+oracle."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from oracle import coracle, loglik as OL, ordering as O, preprocess as P
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _t(a, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device=DEV)
+
+
+def _blocks(n, d, bc, seed, zmax=1.0):
+    g = W.rng(seed)
+    s = g.random((n, d))
+    if d == 3:
+        s[:, 2] *= zmax
+    wscale = [1.0, 1.0, 5.0][:d] if d == 3 else [1.0] * d
+    labels, _ = P.kmeans(s, wscale, W.kmeans_init(n, bc, seed), 10)
+    perm, bp = P.order_blocks(labels, W.block_permutation(bc, seed))
+    return s[perm], bp, wscale
+
+
+@pytest.mark.parametrize("method", ["morton", "maxmin"])
+@pytest.mark.parametrize("n,d,bc", [(3000, 2, 300), (20000, 2, 2000), (6000, 3, 500), (50, 2, 1), (400, 1, 37)])
+def test_reorder_matches_oracle(method, n, d, bc):
+    from paper_2410_04477_amd import api
+    lp, bp, wscale = _blocks(n, d, bc, 300 + n + d, 0.2)
+    order_o, perm_o, bp_o = O.reorder(lp, bp, wscale, method)
+    order, perm, bpg = api.reorder_blocks(_t(lp), _t(bp, torch.int32), method, wscale)
+    assert np.array_equal(order.cpu().numpy(), order_o)
+    assert np.array_equal(perm.cpu().numpy(), perm_o)
+    assert np.array_equal(bpg.cpu().numpy(), bp_o)
+
+
+def test_ordering_kl_study():
+    """n = 8,000 points in the unit square, nu = 1.5, 500 and 2,000 blocks, m = 30:
+    KL = l_exact(theta; 0) - l_BV(theta; 0) per ordering, the exact term by the
+    GPU's large-block kernel (one block of all points), the block Vecchia term
+    by the one-wave kernels; both against the oracle."""
+    from paper_2410_04477_amd import api
+    th = W.Theta(1.0, 0.052537, 1e-6, 1.5)
+    n = 8000
+    g = W.rng(311)
+    s = g.random((n, 2))
+    zero = _t(np.zeros(n))
+    # exact: one block holding every point, no neighbours
+    bp1, np1 = _t(np.array([0, n]), torch.int32), _t(np.array([0, 0]), torch.int32)
+    plan1 = api.Plan(bp1, np1, n, 1)
+    ex_gpu = float(api.loglik(plan1, _t(s), zero, _t(np.zeros(1), torch.int32), [th])[0][0])
+    ex_or = OL.exact_loglik(s, np.zeros(n), th)
+    assert abs(ex_gpu - ex_or) <= 1e-10 * abs(ex_or)
+    rows = []
+    for bc in (500, 2000):
+        labels, _ = P.kmeans(s, [1.0, 1.0], W.kmeans_init(n, bc, 312), 10)
+        perm, bp = P.order_blocks(labels, W.block_permutation(bc, 312))
+        lp = s[perm]
+        for method in ("random", "morton", "maxmin"):
+            if method == "random":
+                lpo, bpo = lp, bp
+            else:
+                _, perm_g, bpo_g = api.reorder_blocks(_t(lp), _t(bp, torch.int32), method, [1.0, 1.0])
+                lpo, bpo = lp[perm_g.cpu().numpy()], bpo_g.cpu().numpy()
+            npt, nid = api.neighbors(_t(lpo), _t(bpo, torch.int32), 30, [1.0, 1.0])
+            plan = api.Plan(_t(bpo, torch.int32), npt, n, 1)
+            bv_gpu = float(api.loglik(plan, _t(lpo), zero, nid, [th])[0][0])
+            npo, nio = P.block_neighbors(lpo, bpo, [1.0, 1.0], 30)
+            bv_or = coracle.loglik(lpo, np.zeros(n), bpo, npo, nio, th)
+            kl_gpu, kl_or = ex_gpu - bv_gpu, ex_or - bv_or
+            rows.append((bc, method, kl_gpu))
+            assert kl_gpu >= 0.0
+            assert abs(kl_gpu - kl_or) <= 1e-6 * max(1.0, kl_or)
+    for r in rows:
+        print(f"bc={r[0]} {r[1]}: KL {r[2]:.3f}")
