@@ -239,6 +239,17 @@ def main() -> int:
     if n_new > 0:
         prediction = bench_prediction(model, locs_new, y_new, w, th0, metric, args.steps, dev)
 
+    # ---- block orderings (preprocessing, untimed in the step): Morton, maxmin --
+    t_order = {}
+    if not args.no_prediction:
+        for method in ("morton", "maxmin"):
+            log(f"reordering {plan.bc} blocks: {method}")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            api.reorder_blocks(model.locs_perm, plan.block_ptr, method, metric)
+            torch.cuda.synchronize()
+            t_order[f"reorder_{method}"] = time.perf_counter() - t0
+
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same blocks --
     cpu = None
     if not args.no_cpu_baseline:
@@ -269,7 +280,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "variants": variants,
         "accuracy": accuracy,
-        "setup_s": {"simulate": t_sim, "preprocess": t_pre},
+        "setup_s": {"simulate": t_sim, "preprocess": t_pre, **t_order},
         "prediction": prediction,
     }
     if args.copy_calibration:

@@ -943,7 +943,8 @@ __global__ void morton_kernel(const double* __restrict__ cen, int bc, int d, dou
 // blocks placed (ties: lowest index).  mind < 0 marks placed blocks.
 constexpr int kMaxminThreads = 1024;
 __global__ void __launch_bounds__(kMaxminThreads)
-maxmin_kernel(const double* __restrict__ cen, int bc, int d, double* __restrict__ mind, int64_t* __restrict__ order) {
+maxmin_kernel(const double* __restrict__ cen, int bc, int d, double* __restrict__ mind, int64_t* __restrict__ order,
+              int steps, int* __restrict__ cur_out) {
 #pragma clang fp contract(off)
   __shared__ double sv[kMaxminThreads];
   __shared__ int si[kMaxminThreads];
@@ -991,9 +992,10 @@ maxmin_kernel(const double* __restrict__ cen, int bc, int d, double* __restrict_
     }
   }
   int cur = reduce_pick(bv0, bi, false);
-  for (int step = 0; step < bc; ++step) {
+  if (t == 0) cur_out[0] = cur;
+  for (int step = 0; step < steps; ++step) {
     if (t == 0) order[step] = cur;
-    if (step == bc - 1) break;
+    if (step == steps - 1) break;
     const double c[3] = {cen[(size_t)cur * d], d > 1 ? cen[(size_t)cur * d + 1] : 0.0, d > 2 ? cen[(size_t)cur * d + 2] : 0.0};
     double best = -1.0;
     int besti = -1;
@@ -1016,6 +1018,92 @@ maxmin_kernel(const double* __restrict__ cen, int bc, int d, double* __restrict_
   }
 }
 
+// Maxmin for many blocks: one launch pair per step over the whole device.
+// Step: every thread updates one block's minimum distance with the block just
+// placed (cur[0]) and the workgroup's best candidate goes to part; pick: one
+// workgroup reduces the parts (ties: lowest index) and places the winner.
+constexpr int kMaxminStepThreads = 256;
+__global__ void __launch_bounds__(kMaxminStepThreads)
+maxmin_step_kernel(const double* __restrict__ cen, int bc, int d, double* __restrict__ mind,
+                   const int* __restrict__ cur, int first_step, double* __restrict__ part_val,
+                   int* __restrict__ part_idx) {
+#pragma clang fp contract(off)
+  __shared__ double sv[kMaxminStepThreads];
+  __shared__ int si[kMaxminStepThreads];
+  const double one[3] = {1.0, 1.0, 1.0};
+  const int t = threadIdx.x, j = blockIdx.x * kMaxminStepThreads + t;
+  const int c0 = cur[0];
+  double m = -1.0;
+  int mi = -1;
+  if (j < bc) {
+    if (j == c0) {
+      m = -1.0;
+    } else {
+      const double c[3] = {cen[(size_t)c0 * d], d > 1 ? cen[(size_t)c0 * d + 1] : 0.0,
+                           d > 2 ? cen[(size_t)c0 * d + 2] : 0.0};
+      const double dj = sqdist_fixed(c, cen, j, d, one);
+      const double old = mind[j];
+      m = first_step ? dj : (old < 0.0 ? old : fmin(old, dj));
+    }
+    mind[j] = m;
+    if (m >= 0.0) mi = j;
+  }
+  sv[t] = m;
+  si[t] = mi;
+  __syncthreads();
+  for (int s = kMaxminStepThreads / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      const double a = sv[t], b = sv[t + s];
+      const int ia = si[t], ib = si[t + s];
+      if (ib >= 0 && (ia < 0 || b > a || (b == a && ib < ia))) {
+        sv[t] = b;
+        si[t] = ib;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    part_val[blockIdx.x] = sv[0];
+    part_idx[blockIdx.x] = si[0];
+  }
+}
+
+__global__ void __launch_bounds__(kMaxminThreads)
+maxmin_pick_kernel(const double* __restrict__ part_val, const int* __restrict__ part_idx, int nb,
+                   int* __restrict__ cur, int64_t* __restrict__ order, int step) {
+  __shared__ double sv[kMaxminThreads];
+  __shared__ int si[kMaxminThreads];
+  const int t = threadIdx.x;
+  double best = -1.0;
+  int bi = -1;
+  for (int k = t; k < nb; k += kMaxminThreads) {
+    const double v = part_val[k];
+    const int i = part_idx[k];
+    if (i >= 0 && (bi < 0 || v > best || (v == best && i < bi))) {
+      best = v;
+      bi = i;
+    }
+  }
+  sv[t] = best;
+  si[t] = bi;
+  __syncthreads();
+  for (int s = kMaxminThreads / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      const double a = sv[t], b = sv[t + s];
+      const int ia = si[t], ib = si[t + s];
+      if (ib >= 0 && (ia < 0 || b > a || (b == a && ib < ia))) {
+        sv[t] = b;
+        si[t] = ib;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    cur[0] = si[0];
+    order[step] = si[0];
+  }
+}
+
 __global__ void block_sizes_kernel(const int* __restrict__ block_ptr, const int64_t* __restrict__ order, int bc,
                                    int* __restrict__ sizes) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1034,7 +1122,7 @@ __global__ void gather_blocks_kernel(const int* __restrict__ block_ptr, const in
 
 namespace {
 struct OrderLayout {
-  size_t cen, key, key2, idx, idx2, mind, sizes, part, sort, scan, total;
+  size_t cen, key, key2, idx, idx2, mind, sizes, pval, pidx, part, sort, scan, total;
 };
 OrderLayout order_layout(int64_t bc, int d) {
   OrderLayout L;
@@ -1046,6 +1134,8 @@ OrderLayout order_layout(int64_t bc, int d) {
   L.idx2 = o;  o = al256(o + sizeof(int64_t) * (size_t)bc);
   L.mind = o;  o = al256(o + sizeof(double) * (size_t)bc);
   L.sizes = o; o = al256(o + sizeof(int) * (size_t)(bc + 1));
+  L.pval = o;  o = al256(o + sizeof(double) * (size_t)(bc / kMaxminStepThreads + 1));
+  L.pidx = o;  o = al256(o + sizeof(int) * (size_t)(bc / kMaxminStepThreads + 1) + 64);
   L.part = o;  o = al256(o + sizeof(double) * 6 * 1024);
   size_t st = 0, sc = 0;
   hipcub::DeviceRadixSort::SortPairs((void*)nullptr, st, (const unsigned long long*)nullptr,
@@ -1100,9 +1190,25 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
     PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key,
                                               at<unsigned long long>(workspace, L.key2), idx, order, ib, 0, 64, s));
   } else {
-    hipLaunchKernelGGL(maxmin_kernel, dim3(1), dim3(kMaxminThreads), 0, s, cen, ib, d,
-                       at<double>(workspace, L.mind), order);
+    // up to 8192 blocks one workgroup does every step; above, one launch pair
+    // per step spreads the O(bc) distance updates over the device
+    double* mind = at<double>(workspace, L.mind);
+    double* pval = at<double>(workspace, L.pval);
+    int* pidx = at<int>(workspace, L.pidx);
+    int* cur = pidx + (bc / kMaxminStepThreads + 1);
+    const bool one_wg = bc <= 8192;
+    hipLaunchKernelGGL(maxmin_kernel, dim3(1), dim3(kMaxminThreads), 0, s, cen, ib, d, mind, order,
+                       one_wg ? ib : 1, cur);
     PCHECK(hipGetLastError());
+    if (!one_wg) {
+      const int nb = cdiv64(bc, kMaxminStepThreads);
+      for (int step = 1; step < ib; ++step) {
+        hipLaunchKernelGGL(maxmin_step_kernel, dim3(nb), dim3(kMaxminStepThreads), 0, s, cen, ib, d, mind, cur,
+                           step == 1 ? 1 : 0, pval, pidx);
+        hipLaunchKernelGGL(maxmin_pick_kernel, dim3(1), dim3(kMaxminThreads), 0, s, pval, pidx, nb, cur, order, step);
+      }
+      PCHECK(hipGetLastError());
+    }
   }
   int* sizes = at<int>(workspace, L.sizes);
   hipLaunchKernelGGL(block_sizes_kernel, dim3(cdiv64(bc + 1, 256)), dim3(256), 0, s, block_ptr, order, ib, sizes);

@@ -29,7 +29,8 @@ def _blocks(n, d, bc, seed, zmax=1.0):
 
 
 @pytest.mark.parametrize("method", ["morton", "maxmin"])
-@pytest.mark.parametrize("n,d,bc", [(3000, 2, 300), (20000, 2, 2000), (6000, 3, 500), (50, 2, 1), (400, 1, 37)])
+@pytest.mark.parametrize("n,d,bc", [(3000, 2, 300), (20000, 2, 2000), (6000, 3, 500), (50, 2, 1), (400, 1, 37),
+                                    (60000, 2, 10000)])
 def test_reorder_matches_oracle(method, n, d, bc):
     from paper_2410_04477_amd import api
     lp, bp, wscale = _blocks(n, d, bc, 300 + n + d, 0.2)
