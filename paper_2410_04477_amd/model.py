@@ -17,12 +17,14 @@ class BlockVecchia:
 
     locs: n x d (original order), y: n.  init_idx / block_perm are the
     K-means start points and the random block order (drawn by the caller).
+    ordering: "random" (that order), "morton" or "maxmin" (block centroids).
     aniso: per-axis range multipliers; neighbour search and K-means use the
-    metric 1/aniso.  nu is fixed (0.5, 1.5 or 2.5)."""
+    metric 1/aniso.  nu is fixed per model: 0.5, 1.5, 2.5 in closed form, any
+    other value in [0.05, 10] through the Bessel form (engine "mfma")."""
 
     def __init__(self, locs, y, bc: int, m: int, nu: float, init_idx, block_perm,
                  aniso: Sequence[float] = (1.0, 1.0, 1.0), kmeans_iters: int = 30, max_theta: int = 1,
-                 device: str = "cuda", engine: str = "mfma"):
+                 device: str = "cuda", engine: str = "mfma", ordering: str = "random"):
         dev = torch.device(device)
         def t(a, dt):
             a = a if isinstance(a, torch.Tensor) else torch.as_tensor(np.asarray(a))
@@ -35,6 +37,10 @@ class BlockVecchia:
         self.metric = [1.0 / a for a in self.aniso[: self.d]]
         self.perm, self.block_ptr, self.kmeans_iters = api.blocks(
             locs_t, bc, t(init_idx, torch.int64), t(block_perm, torch.int64), self.metric, kmeans_iters)
+        if ordering != "random":
+            lp = api.permute_rows(locs_t, self.perm)
+            _, pp, self.block_ptr = api.reorder_blocks(lp, self.block_ptr, ordering, self.metric)
+            self.perm = self.perm[pp]   # compose: block order -> original index
         self.locs_perm = api.permute_rows(locs_t, self.perm)
         self.y_perm = api.permute_rows(y_t, self.perm)
         self.nbr_ptr, self.nbr_idx = api.neighbors(self.locs_perm, self.block_ptr, m, self.metric)
@@ -60,6 +66,28 @@ class BlockVecchia:
 
     def theta(self, sigma2: float, range_: float, nugget: float):
         return (float(sigma2), float(range_), float(nugget), self.nu, self.aniso)
+
+    def predict(self, locs_new, bc: int, m: int, theta, init_idx, block_perm, want_cov: bool = False,
+                kmeans_iters: int = 30):
+        """Block Vecchia prediction (Alg. 2) at new locations (original order):
+        K-means blocks of the new points, the m nearest observations of each
+        block, conditional means and variances.  Returns (mean, var, cov or
+        None, perm, block_ptr): mean and var in the block order of the new
+        points, perm[i] = original index of the i-th, cov per block."""
+        dev = self.locs_perm.device
+        ln = torch.as_tensor(np.asarray(locs_new) if not isinstance(locs_new, torch.Tensor) else locs_new)
+        ln = ln.to(device=dev, dtype=torch.float64).contiguous()
+        k = ln.shape[0]
+        perm, bp, _ = api.blocks(ln, bc, torch.as_tensor(np.asarray(init_idx), device=dev, dtype=torch.int64),
+                                 torch.as_tensor(np.asarray(block_perm), device=dev, dtype=torch.int64),
+                                 self.metric, kmeans_iters)
+        lnp = api.permute_rows(ln, perm)
+        npt, nid = api.pred_neighbors(self.locs_perm, lnp, bp, m, self.metric)
+        if nid.numel() == 0:
+            nid = torch.zeros(1, dtype=torch.int32, device=dev)
+        plan = api.Plan(bp, npt, k, 1, "mfma", predict=True)
+        mean, var, cov = api.predict(plan, self.locs_perm, self.y_perm, lnp, nid, theta, want_cov)
+        return mean, var, cov, perm, bp
 
     def loglik(self, thetas, precision: str = "fp64", want_partial: bool = False):
         return api.loglik(self.plan, self.locs_perm, self.y_perm, self.nbr_idx, thetas, precision, want_partial)

@@ -213,3 +213,35 @@ def test_paper_prediction_setting_coverage():
     print(f"GPU pipeline PICP {full['picp']:.4f} MSPE {full['mspe']:.5f}")
     assert 0.93 <= full["picp"] <= 0.97
     assert full["mspe"] == pytest.approx(float(var_g.mean()), rel=0.15)
+
+
+def test_model_level_predict_and_ordering():
+    """BlockVecchia with a maxmin block order gives the oracle's likelihood on
+    the same blocks, and its predict() matches the oracle's prediction."""
+    from paper_2410_04477_amd.model import BlockVecchia
+    from oracle import loglik as OL, ordering as O
+    th = W.Theta(1.0, 0.1, 1e-3, 1.5)
+    g = W.rng(171)
+    s = g.random((2000, 2))
+    from oracle import simulate
+    y = simulate.exact_gp(s, th, g.standard_normal(2000))
+    bv = BlockVecchia(s, y, 100, 30, 1.5, W.kmeans_init(2000, 100, 3), W.block_permutation(100, 3),
+                      ordering="maxmin")
+    lp, yp = bv.locs_perm.cpu().numpy(), bv.y_perm.cpu().numpy()
+    bp = bv.block_ptr.cpu().numpy()
+    # the order is the oracle's maxmin order of these blocks' centroids
+    cen = P.block_centroids(lp, bp, [1.0, 1.0])
+    assert np.array_equal(O.maxmin_order(cen), np.arange(bp.size - 1))
+    npt, nid = P.block_neighbors(lp, bp, [1.0, 1.0], 30)
+    ref = OL.loglik(lp, yp, bp, npt, nid, th)
+    ll, _, _ = bv.loglik([(1.0, 0.1, 1e-3, 1.5)])
+    assert abs(float(ll[0]) - ref) <= 1e-8 * abs(ref)
+    s_new = g.random((300, 2))
+    mean, var, _, perm, bpn = bv.predict(s_new, 30, 25, (1.0, 0.1, 1e-3, 1.5), W.kmeans_init(300, 30, 4),
+                                         W.block_permutation(30, 4))
+    sn = s_new[perm.cpu().numpy()]
+    bpn = bpn.cpu().numpy()
+    pnp, pni = PR.pred_neighbors(lp, sn, bpn, [1.0, 1.0], 25)
+    mo, vo, _ = PR.predict(lp, yp, sn, bpn, pnp, pni, th)
+    assert np.max(np.abs(mean.cpu().numpy() - mo)) <= 1e-9
+    assert np.max(np.abs(var.cpu().numpy() - vo)) <= 1e-10
