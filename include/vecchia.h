@@ -62,9 +62,14 @@ typedef enum {
 /* Matern parameters, eq. (maternkernel), plus a nugget and per-axis ranges:
  *   C(s_i, s_j) = sigma2 * rho_nu(h / range) + nugget * [i == j],
  *   h = || (s_i - s_j) / aniso ||  (componentwise division; aniso = {1,1,1}
- *   is isotropic).  nu must be 0.5, 1.5 or 2.5 (closed forms
- *   rho = e^-x, (1+x) e^-x, (1 + x + x^2/3) e^-x).  The nugget applies to
- *   same-index pairs only (not to distinct points at distance zero). */
+ *   is isotropic).  nu = 0.5, 1.5, 2.5 use the closed forms rho = e^-x,
+ *   (1+x) e^-x, (1 + x + x^2/3) e^-x; any other nu in [0.05, 10] uses
+ *   rho = 2^(1-nu)/Gamma(nu) x^nu K_nu(x), evaluated in FP64 (Temme's series,
+ *   Steed's continued fraction, upward recurrence) by the one-wave kernels
+ *   only: other engines, blocks above VECCHIA_MAX_JOINT and the simulator
+ *   return VECCHIA_EUNSUPPORTED for it, as for nu outside [0.05, 10].  The
+ *   nugget applies to same-index pairs only (not to distinct points at
+ *   distance zero). */
 typedef struct {
   double sigma2;
   double range;
