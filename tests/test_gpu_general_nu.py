@@ -132,3 +132,20 @@ def test_error_paths():
     ll, _, _ = api.loglik(plan, lp, yp, nid, [th])
     ref = OL.loglik(pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"], th)
     assert abs(float(ll[0]) - ref) <= 1e-8 * abs(ref)
+
+
+def test_mle_with_bessel_form():
+    """L-BFGS on (sigma2, range, nugget) at nu = 1.0 (Bessel-form kernels):
+    the fit is at least as likely as the truth and better than the start."""
+    from paper_2410_04477_amd import mle
+    from paper_2410_04477_amd.model import BlockVecchia
+    th = W.Theta(1.2, 0.1, 0.01, 1.0)
+    pb = problem("gnu-mle", 2000, 2, 200, 30, th, 83)
+    mod = BlockVecchia.from_prepared(_t(pb["locs_perm"]), _t(pb["y_perm"]), _t(pb["block_ptr"], torch.int32),
+                                     _t(pb["nbr_ptr"], torch.int32), _t(pb["nbr_idx"], torch.int32), 1.0)
+    res = mle.fit(mod, (1.0, 0.05, 0.05), "fp64", max_evals=80)
+    ll_true = float(mod.loglik([mod.theta(th.sigma2, th.beta, th.nugget)])[0][0])
+    ll0 = float(mod.loglik([mod.theta(1.0, 0.05, 0.05)])[0][0])
+    assert res.loglik >= ll_true - 1e-6 * abs(ll_true)
+    assert res.loglik > ll0
+    assert 0.5 < res.theta[0] / th.sigma2 < 2.0 and 0.5 < res.theta[1] / th.beta < 2.0
