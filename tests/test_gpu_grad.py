@@ -173,6 +173,10 @@ def test_c4_full_size_gradient_vs_oracle():
         ref_ll = coracle.loglik(pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"], th)
         assert abs(float(ll[i]) - ref_ll) <= 1e-8 * abs(ref_ll)
         assert abs(float(ll32[i]) - ref_ll) <= 1e-4 * abs(ref_ll)
+        print(f"C4 theta {i}: loglik rel err fp64 {abs(float(ll[i]) - ref_ll) / abs(ref_ll):.2e} fp32-bulk "
+              f"{abs(float(ll32[i]) - ref_ll) / abs(ref_ll):.2e}; gradient rel err fp64 "
+              f"{_rel(g[i].cpu().numpy(), ref):.2e}, fp32-bulk per component vs sum|dl_i| "
+              f"{np.array2string(np.abs(g32[i].cpu().numpy() - ref) / scale, precision=2)}")
 
 
 def test_simulator_matches_oracle():

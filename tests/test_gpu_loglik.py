@@ -46,7 +46,11 @@ def _check_fp64(pb, thetas, engine="mfma"):
 def test_fp64_c1_all_grid_thetas():
     w = W.C1
     pb = workload_problem(w, ysim="exact")
-    _check_fp64(pb, W.theta_grid_c1())
+    thetas = W.theta_grid_c1()
+    ll = _check_fp64(pb, thetas)
+    worst = max(abs(ll[t] - oracle_sum(oracle_terms(pb, th))) / abs(oracle_sum(oracle_terms(pb, th)))
+                for t, th in enumerate(thetas))
+    print(f"C1 worst rel err fp64 {worst:.2e} over {len(thetas)} thetas")
 
 
 @pytest.mark.parametrize("engine", ENGINES)
@@ -55,9 +59,13 @@ def test_fp32_bulk_c1_grid(engine):
     pb = workload_problem(w, ysim="exact")
     thetas = W.theta_grid_c1()
     ll, cnt, _, _ = _gpu(pb, thetas, "fp32", engine=engine)
+    worst = 0.0
     for t, th in enumerate(thetas):
         ref = oracle_sum(oracle_terms(pb, th))
+        worst = max(worst, abs(ll[t] - ref) / abs(ref))
         assert abs(ll[t] - ref) <= 1e-4 * abs(ref), (t, ll[t], ref, cnt[t])
+    print(f"C1 worst rel err fp32-bulk ({engine}) {worst:.2e}; refactored {int(cnt[:, 0].sum())} of "
+          f"{len(thetas) * (pb['block_ptr'].size - 1)}")
 
 
 @pytest.mark.parametrize("nu,d", [(0.5, 2), (1.5, 2), (2.5, 3)])
