@@ -292,6 +292,28 @@ int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const
                         double* loglik, double* grad, int32_t* counters, double* partial, double* gpartial,
                         void* stream);
 
+/* ------------------------------------------------------------ loglik_dnu --
+ * Derivative of the log-likelihood w.r.t. the Matern smoothness nu (eq.
+ * (maternkernel)), for estimating nu together with the other parameters as
+ * in Section 3.  A central difference of two FP64 evaluations at
+ * nu (1 + rel_step) and nu (1 - rel_step), each clipped to [0.05, 10]; both
+ * use the Bessel form, so the plan must use engine VECCHIA_ENGINE_MFMA with
+ * no block above the one-wave limit.  Truncation error is of order
+ * (rel_step nu)^2 |d3 l / d nu3| / 6, rounding error of order
+ * 1e-16 |l| / (rel_step nu); rel_step = 1e-4 balances them for FP64.
+ * There is no adjoint for nu (d K_nu / d nu has no closed form).
+ *   theta, ntheta   host, as vecchia_loglik (precision is always FP64)
+ *   rel_step        relative step, in (0, 0.1]
+ *   dnu             out, device, ntheta doubles
+ *   tmp             device scratch owned by the caller, 2*ntheta doubles
+ *                   (the two log-likelihoods of each theta)
+ * Returns VECCHIA_EINVAL for NULL pointers or rel_step outside (0, 0.1], and
+ * the status vecchia_loglik gives for the shifted theta otherwise. */
+int vecchia_loglik_dnu(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                       const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                       const vecchia_theta* theta, int32_t ntheta, double rel_step, double* dnu, double* tmp,
+                       void* stream);
+
 /* ------------------------------------------------------------ prediction --
  * Block Vecchia prediction (Section 2.4, Alg. 2).  The n_new new locations
  * are grouped into blocks B*_1..B*_bc (for instance vecchia_blocks on them,

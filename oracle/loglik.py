@@ -10,6 +10,8 @@
 * grad_trace is the textbook Gaussian log-density gradient applied to each
   block's joint and neighbour densities (the block term of eq.
   (vecchia-vector) is log p(y_J) - log p(y_N)).
+* grad_nu_trace is the same trace formula for the smoothness nu, with
+  d C / d nu from the integral form of d K_nu / d nu (matern.drho_dnu).
 * kl_divergence is eq. (kl-gaussian-vecchia).
 """
 from __future__ import annotations
@@ -123,6 +125,31 @@ def grad_trace(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta, blocks=Non
         g = _logpdf_grad(locs_perm[J], y_perm[J], theta)
         if nn.size:
             g = g - _logpdf_grad(locs_perm[nn], y_perm[nn], theta)
+        out.append(g)
+    return np.array(out)
+
+
+def _logpdf_dnu(s, y, theta) -> float:
+    """d/dnu of log N(y; 0, K(theta)): 0.5 tr[(alpha alpha^T - K^-1) dK/dnu]."""
+    K = matern.cov(s, s, theta, same=True)
+    Kinv = np.linalg.inv(K)
+    alpha = Kinv @ y
+    W = np.outer(alpha, alpha) - Kinv
+    return 0.5 * float(np.sum(W * matern.dcov_dnu(s, s, theta)))
+
+
+def grad_nu_trace(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta, blocks=None) -> np.ndarray:
+    """Per-block d l_i / d nu of l_i = log p(y_J) - log p(y_N)."""
+    bc = block_ptr.size - 1
+    sel = range(bc) if blocks is None else blocks
+    out = []
+    for i in sel:
+        a, b = int(block_ptr[i]), int(block_ptr[i + 1])
+        nn = np.asarray(nbr_idx[nbr_ptr[i]:nbr_ptr[i + 1]], dtype=np.int64)
+        J = np.concatenate([nn, np.arange(a, b)])
+        g = _logpdf_dnu(locs_perm[J], y_perm[J], theta)
+        if nn.size:
+            g -= _logpdf_dnu(locs_perm[nn], y_perm[nn], theta)
         out.append(g)
     return np.array(out)
 

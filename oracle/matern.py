@@ -11,7 +11,7 @@ from __future__ import annotations
 import math
 
 import numpy as np
-from scipy import special
+from scipy import integrate, special
 
 
 def rho_general(x, nu: float):
@@ -62,6 +62,47 @@ def drho_dbeta(x, beta: float, nu: float):
     else:
         return drho_dbeta_general(x, beta, nu)
     return (x / beta) * g
+
+
+def dk_dnu(x: float, nu: float) -> float:
+    """d K_nu(x) / d nu from the integral form K_nu(x) = int_0^inf exp(-x cosh t)
+    cosh(nu t) dt (a textbook representation), differentiated under the
+    integral: int_0^inf t sinh(nu t) exp(-x cosh t) dt, by adaptive quadrature.
+    The integrand is formed in log space so that large nu t cannot overflow."""
+    def f(t):
+        if t == 0.0:
+            return 0.0
+        lt = math.log(t) - x * math.cosh(t)
+        return 0.5 * (math.exp(lt + nu * t) - math.exp(lt - nu * t))
+    # cut-off T where the integrand is below exp(-745) relative to its peak:
+    # x cosh T >= nu T + 800 (fixed point of T = log(2 (nu T + 800) / x))
+    T = 10.0
+    for _ in range(60):
+        T = math.log(2.0 * (nu * T + 800.0) / x)
+    val, _ = integrate.quad(f, 0.0, T, epsabs=0.0, epsrel=1e-13, limit=400)
+    return val
+
+
+def drho_dnu(x, nu: float):
+    """d rho / d nu of rho = c(nu) x^nu K_nu(x), c(nu) = 2^(1-nu) / Gamma(nu):
+    rho (log(x / 2) - psi(nu)) + c(nu) x^nu dK_nu/dnu; zero at x = 0 (rho(0) = 1
+    for every nu)."""
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    c = 2.0 ** (1.0 - nu) / special.gamma(nu)
+    for idx in zip(*np.nonzero(x > 0)):
+        xv = float(x[idx])
+        r = c * xv ** nu * special.kv(nu, xv)
+        out[idx] = r * (math.log(xv / 2.0) - special.digamma(nu)) + c * xv ** nu * dk_dnu(xv, nu)
+    return out
+
+
+def dcov_dnu(s1, s2, theta) -> np.ndarray:
+    """d C / d nu = sigma2 d rho / d nu (the nugget does not depend on nu).
+    Distinct distances are evaluated once."""
+    h = scaled_dist(s1, s2, theta.aniso) / theta.beta
+    u, inv = np.unique(h, return_inverse=True)
+    return theta.sigma2 * drho_dnu(u, theta.nu)[inv].reshape(h.shape)
 
 
 def scaled_dist(s1: np.ndarray, s2: np.ndarray, aniso) -> np.ndarray:

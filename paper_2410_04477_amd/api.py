@@ -216,6 +216,24 @@ def loglik(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_idx: t
     return out, cnt, part
 
 
+def loglik_dnu(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_idx: torch.Tensor,
+               thetas: Iterable, rel_step: float = 1e-4):
+    """d l / d nu for each theta (FP64 central difference in the library).
+    Returns dnu[ntheta] f64 as a device tensor."""
+    _dev_check(locs_perm, y_perm, nbr_idx)
+    th = [make_theta(t) for t in thetas]
+    nt = len(th)
+    arr = (L.Theta * nt)(*th)
+    dev = locs_perm.device
+    out = torch.empty(nt, dtype=torch.float64, device=dev)
+    tmp = torch.empty(2 * nt, dtype=torch.float64, device=dev)
+    d = 1 if locs_perm.dim() == 1 else locs_perm.shape[1]
+    L.check(L.lib().vecchia_loglik_dnu(ctypes.byref(plan.c), _p(locs_perm), _p(y_perm), d, _p(plan.block_ptr),
+                                       _p(plan.nbr_ptr), _p(nbr_idx), arr, nt, float(rel_step), _p(out), _p(tmp),
+                                       _stream(dev)), "vecchia_loglik_dnu")
+    return out
+
+
 def loglik_grad(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_idx: torch.Tensor,
                 thetas: Iterable, precision: str = "fp64", want_partial: bool = False):
     """Log-likelihood and its gradient w.r.t. (sigma2, range, nugget) for each theta.

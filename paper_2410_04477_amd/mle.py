@@ -1,5 +1,6 @@
-"""Maximum-likelihood estimation of (sigma2, range, nugget) with L-BFGS on
-log-parameters, driven by the adjoint gradient (VecchiaLogLik)."""
+"""Maximum-likelihood estimation of (sigma2, range, nugget), and optionally
+the smoothness nu, with L-BFGS on transformed parameters, driven by the
+adjoint gradient (VecchiaLogLik) and the library's d l / d nu."""
 from __future__ import annotations
 
 import dataclasses
@@ -8,14 +9,15 @@ import time
 
 import torch
 
-from .model import BlockVecchia, vecchia_loglik
+from .model import BlockVecchia, vecchia_loglik, vecchia_loglik_nu
 
 NUGGET_FLOOR = 1e-8  # log-parametrisation floor: eta_3 = log(nugget + floor)
+NU_LO, NU_HI = 0.06, 9.5   # nu = NU_LO + (NU_HI - NU_LO) sigmoid(eta_4), inside the Bessel form's [0.05, 10]
 
 
 @dataclasses.dataclass
 class MLEResult:
-    theta: tuple          # (sigma2, range, nugget)
+    theta: tuple          # (sigma2, range, nugget), plus nu when it is estimated
     loglik: float
     evals: int
     iters: int
@@ -23,22 +25,35 @@ class MLEResult:
     converged: bool
 
 
+def _nu_to_eta(nu: float) -> float:
+    u = (nu - NU_LO) / (NU_HI - NU_LO)
+    return math.log(u / (1.0 - u))
+
+
 def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 200, tol_rel: float = 1e-10,
-        history: int = 10, polish_evals: int = 30) -> MLEResult:
+        history: int = 10, polish_evals: int = 30, estimate_nu: bool = False) -> MLEResult:
     """L-BFGS (strong Wolfe line search) on eta = log(sigma2, range, nugget + floor),
     minimising -l / n.  Stops on relative change < tol_rel, small gradient, or
     max_evals evaluations.  With an FP32-bulk precision, a short FP64 L-BFGS
     pass (at most polish_evals evaluations) starts from the FP32 optimum: the
     FP32 gradient's rounding error can stop the line search early near the
-    optimum, where the exact gradient is small."""
+    optimum, where the exact gradient is small.
+    estimate_nu: nu joins the parameters (the paper estimates it with the
+    others), through eta_4 = logit((nu - NU_LO) / (NU_HI - NU_LO)); theta0 may
+    then carry a fourth entry, the starting nu (else the model's)."""
     if precision != "fp64" and polish_evals > 0:
-        first = fit(model, theta0, precision, max_evals, tol_rel, history, 0)
-        second = fit(model, first.theta, "fp64", polish_evals, tol_rel, history, 0)
+        first = fit(model, theta0, precision, max_evals, tol_rel, history, 0, estimate_nu)
+        second = fit(model, first.theta, "fp64", polish_evals, tol_rel, history, 0, estimate_nu)
         return MLEResult(second.theta, second.loglik, first.evals + second.evals, first.iters + second.iters,
                          first.seconds + second.seconds, second.converged)
-    s2, rg, nug = (float(v) for v in theta0)
-    eta = torch.tensor([math.log(s2), math.log(rg), math.log(nug + NUGGET_FLOOR)], dtype=torch.float64,
-                       requires_grad=True)
+    s2, rg, nug = (float(v) for v in theta0[:3])
+    e0 = [math.log(s2), math.log(rg), math.log(nug + NUGGET_FLOOR)]
+    if estimate_nu:
+        nu0 = float(theta0[3]) if len(theta0) > 3 else model.nu
+        if not NU_LO < nu0 < NU_HI:
+            raise ValueError(f"starting nu {nu0} outside ({NU_LO}, {NU_HI})")
+        e0.append(_nu_to_eta(nu0))
+    eta = torch.tensor(e0, dtype=torch.float64, requires_grad=True)
     opt = torch.optim.LBFGS([eta], lr=1.0, max_iter=max_evals, max_eval=max_evals, history_size=history,
                             tolerance_grad=1e-9, tolerance_change=tol_rel, line_search_fn="strong_wolfe")
     n = model.n
@@ -46,11 +61,16 @@ def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 2
 
     def closure():
         opt.zero_grad()
-        e = torch.exp(eta)
-        params = torch.stack([e[0], e[1], e[2] - NUGGET_FLOOR])
-        ll = vecchia_loglik(params, model, precision)
+        e = torch.exp(eta[:3])
+        if estimate_nu:
+            nu = NU_LO + (NU_HI - NU_LO) * torch.sigmoid(eta[3])
+            params = torch.stack([e[0], e[1], e[2] - NUGGET_FLOOR, nu])
+            ll = vecchia_loglik_nu(params, model, precision)
+        else:
+            params = torch.stack([e[0], e[1], e[2] - NUGGET_FLOOR])
+            ll = vecchia_loglik(params, model, precision)
         if not torch.isfinite(ll):
-            ll = torch.tensor(-1e300, dtype=torch.float64)  # pushes the line search back
+            ll = 0.0 * params.sum() - 1e300   # pushes the line search back (keeps the graph for backward)
         loss = -ll / n
         loss.backward()
         state["evals"] += 1
@@ -60,8 +80,11 @@ def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 2
     t0 = time.perf_counter()
     opt.step(closure)
     dt = time.perf_counter() - t0
-    e = torch.exp(eta.detach())
+    ed = eta.detach()
+    e = torch.exp(ed[:3])
     th = (float(e[0]), float(e[1]), float(e[2] - NUGGET_FLOOR))
+    if estimate_nu:
+        th = th + (float(NU_LO + (NU_HI - NU_LO) * torch.sigmoid(ed[3])),)
     ll = float(model.loglik([model.theta(*th)], precision)[0][0])
     st = opt.state[opt._params[0]]
     return MLEResult(th, ll, state["evals"], int(st.get("n_iter", 0)), dt, state["evals"] < max_evals)

@@ -64,8 +64,8 @@ class BlockVecchia:
         self.plan = api.Plan(block_ptr, nbr_ptr, self.n, max_theta, engine)
         return self
 
-    def theta(self, sigma2: float, range_: float, nugget: float):
-        return (float(sigma2), float(range_), float(nugget), self.nu, self.aniso)
+    def theta(self, sigma2: float, range_: float, nugget: float, nu: Optional[float] = None):
+        return (float(sigma2), float(range_), float(nugget), self.nu if nu is None else float(nu), self.aniso)
 
     def predict(self, locs_new, bc: int, m: int, theta, init_idx, block_perm, want_cov: bool = False,
                 kmeans_iters: int = 30):
@@ -97,6 +97,10 @@ class BlockVecchia:
                                want_partial)
 
 
+    def loglik_dnu(self, thetas, rel_step: float = 1e-4):
+        return api.loglik_dnu(self.plan, self.locs_perm, self.y_perm, self.nbr_idx, thetas, rel_step)
+
+
 class VecchiaLogLik(torch.autograd.Function):
     """l(sigma2, range, nugget) with the hand-written adjoint as its backward.
     The forward evaluates value and gradient in one pass of the library (no
@@ -118,3 +122,28 @@ class VecchiaLogLik(torch.autograd.Function):
 
 def vecchia_loglik(params: torch.Tensor, model: BlockVecchia, precision: str = "fp64") -> torch.Tensor:
     return VecchiaLogLik.apply(params, model, precision)
+
+
+class VecchiaLogLikNu(torch.autograd.Function):
+    """l(sigma2, range, nugget, nu): the adjoint gradient for the first three
+    parameters (in the requested precision) and d l / d nu from the library's
+    FP64 central difference in nu."""
+
+    @staticmethod
+    def forward(ctx, params: torch.Tensor, model: BlockVecchia, precision: str = "fp64"):
+        p = params.detach().to(torch.float64).cpu().tolist()
+        th = model.theta(*p)
+        ll, g, cnt, _, _ = model.loglik_grad([th], precision)
+        dnu = model.loglik_dnu([th])
+        ctx.save_for_backward(torch.cat([g[0], dnu]).to(params.device, params.dtype))
+        ctx.counters = cnt
+        return ll[0].to(params.device, params.dtype)
+
+    @staticmethod
+    def backward(ctx, gout):
+        (g,) = ctx.saved_tensors
+        return gout * g, None, None
+
+
+def vecchia_loglik_nu(params: torch.Tensor, model: BlockVecchia, precision: str = "fp64") -> torch.Tensor:
+    return VecchiaLogLikNu.apply(params, model, precision)

@@ -190,3 +190,19 @@ def test_general_nu_numpy_oracle(nu):
         v, h = getattr(theta, name), 1e-6 * max(getattr(theta, name), 1e-3)
         fd = (OL.loglik(*args, theta.replace(**{name: v + h})) - OL.loglik(*args, theta.replace(**{name: v - h}))) / (2 * h)
         assert g[k] == pytest.approx(fd, rel=1e-5, abs=1e-6)
+
+
+@pytest.mark.parametrize("nu", [0.5, 1.3, 3.3])
+def test_nu_gradient_matches_fd(nu):
+    """d l / d nu by the trace formula (d C / d nu from the integral form of
+    d K_nu / d nu) against central differences of the Cholesky-based
+    log-likelihood in nu, per block."""
+    theta = W.Theta(1.1, 0.08, 2e-3, nu)
+    s, y, pre = _problem(120, 12, 15, theta)
+    lp, yp = pre["locs_perm"], y[pre["perm"]]
+    args = (lp, yp, pre["block_ptr"], pre["nbr_ptr"], pre["nbr_idx"])
+    g = OL.grad_nu_trace(*args, theta)
+    h = 1e-5 * nu
+    fd = (OL.block_terms(*args, theta.replace(nu=nu + h)) - OL.block_terms(*args, theta.replace(nu=nu - h))) / (2 * h)
+    np.testing.assert_allclose(g, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+    assert abs(g.sum() - fd.sum()) <= 1e-6 * np.abs(fd).sum()

@@ -73,3 +73,24 @@ def test_general_derivative_matches_fd_and_closed_forms(nu):
     if nu in (0.5, 1.5, 2.5):
         np.testing.assert_allclose(got, matern.drho_dbeta(h / beta, beta, nu), rtol=1e-12)
         np.testing.assert_allclose(matern.rho_general(h / beta, nu), matern.rho(h / beta, nu), rtol=1e-12)
+
+
+def test_drho_dnu_closed_form_at_one_half():
+    """At nu = 1/2, d K_nu / d nu = sqrt(pi / (2x)) E1(2x) e^x (a textbook
+    special case) and psi(1/2) = -gamma - 2 log 2, so
+    d rho / d nu = e^-x (log(x/2) + gamma + 2 log 2) + e^x E1(2x)."""
+    x = np.array([1e-3, 0.02, 0.3, 1.0, 2.5, 7.0, 25.0])
+    ref = np.exp(-x) * (np.log(x / 2) + np.euler_gamma + 2 * np.log(2.0)) + np.exp(x) * special.exp1(2 * x)
+    np.testing.assert_allclose(matern.drho_dnu(x, 0.5), ref, rtol=1e-11)
+
+
+@pytest.mark.parametrize("nu", [0.07, 0.3, 0.8, 1.0, 1.5, 2.2, 3.7, 7.5, 10.0])
+def test_drho_dnu_matches_fd_of_library_bessel(nu):
+    """The integral form of d rho / d nu against central differences in nu of
+    the library's K_nu; zero at distance zero."""
+    x = np.array([0.0, 1e-4, 0.01, 0.3, 1.0, 2.5, 7.0, 30.0])
+    e = 1e-5 * nu
+    fd = (_bessel_form(x[1:], nu + e) - _bessel_form(x[1:], nu - e)) / (2 * e)
+    got = matern.drho_dnu(x, nu)
+    assert got[0] == 0.0
+    np.testing.assert_allclose(got[1:], fd, rtol=1e-6, atol=1e-9)
