@@ -143,7 +143,11 @@ int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const doubl
  *   VECCHIA_ORDER_MAXMIN  first the block nearest the mean centroid (summed in
  *                         block order), then each next block maximises the
  *                         minimum squared distance to the blocks placed (ties:
- *                         lowest index); one workgroup, O(bc^2) work
+ *                         lowest index); O(bc^2) work, one workgroup up to
+ *                         8,192 blocks, one launch pair per step above
+ *   VECCHIA_ORDER_HILBERT the Morton cells, keyed by their distance along the
+ *                         Hilbert curve of order B (Skilling's transform; in
+ *                         1-D the cell order), sorted by key then block index
  * vecchia_reorder_blocks takes points already grouped into blocks (locs_perm,
  * block_ptr) and returns
  *   block_order    out, bc int64: position -> current block index
@@ -151,9 +155,11 @@ int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const doubl
  *   block_ptr_out  out, bc+1 int32 for the new order
  * Apply point_perm with vecchia_permute, then search neighbours.
  *   workspace  >= vecchia_reorder_blocks_workspace_size(n, bc, d) bytes
- * Synchronises `stream` (Morton: the bounding box goes through the host). */
+ * Synchronises `stream` (Morton, Hilbert: the bounding box goes through the
+ * host). */
 #define VECCHIA_ORDER_MORTON 1
 #define VECCHIA_ORDER_MAXMIN 2
+#define VECCHIA_ORDER_HILBERT 3
 size_t vecchia_reorder_blocks_workspace_size(int64_t n, int64_t bc, int32_t d);
 int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_t d, const double* metric_scale,
                            const int32_t* block_ptr, int64_t bc, int32_t method, int64_t* block_order,

@@ -1,4 +1,4 @@
-"""Block orderings (Section 2.1: Morton and maxmin reorderings of the blocks),
+"""Block orderings (Section 2.1: Morton, Hilbert and maxmin reorderings of the blocks),
 numpy FP64.  The KL divergence used to compare them (eq.
 (kl-gaussian-vecchia)) is loglik.kl_divergence.
 
@@ -12,6 +12,12 @@ Readings where the paper is silent:
     3-D, 63 bits in 1-D), cell = min(floor((c - lo) / (hi - lo) * 2^B), 2^B - 1);
     the key interleaves the bits, axis 0 in the lowest position; blocks are
     sorted by key, ties by block index.
+  * Hilbert: the same cells as Morton, mapped to their distance along a
+    Hilbert curve of order B by Skilling's transform (J. Skilling,
+    "Programming the Hilbert curve", AIP Conf. Proc. 707, 2004): from the top
+    bit down, undo the curve's rotations and reflections, Gray-encode, then
+    read the index bits level by level, axis 0 most significant within a
+    level.  In 1-D the curve is the cell order itself.  Sorted like Morton.
   * Maxmin: the first block is the one whose centroid is nearest the mean of
     the centroids (summed in block order); each next block maximises the minimum squared distance to
     the blocks already placed; ties by lowest block index.  Squared distances
@@ -37,6 +43,54 @@ def morton_keys(cen: np.ndarray) -> np.ndarray:
         for k in range(d):
             keys |= ((cells[:, k] >> np.uint64(b)) & np.uint64(1)) << np.uint64(b * d + k)
     return keys
+
+
+def _cells(cen: np.ndarray):
+    n, d = cen.shape
+    bits = {1: 63, 2: 32, 3: 21}[d]
+    lo, hi = cen.min(0), cen.max(0)
+    ext = np.where(hi > lo, hi - lo, 1.0)
+    scale = float(1 << bits)
+    return np.minimum(np.floor((cen - lo) / ext * scale), scale - 1).astype(np.uint64), bits
+
+
+def hilbert_index(cells: np.ndarray, bits: int) -> np.ndarray:
+    """Distance along the order-`bits` Hilbert curve of integer cells (rows of
+    an n x d uint64 array, each coordinate below 2^bits)."""
+    n, d = cells.shape
+    if d == 1:
+        return cells[:, 0].astype(np.uint64)
+    X = [cells[:, k].astype(np.uint64).copy() for k in range(d)]
+    q = 1 << (bits - 1)
+    while q > 1:
+        Q, P = np.uint64(q), np.uint64(q - 1)
+        for i in range(d):
+            hit = (X[i] & Q) != 0
+            X[0] = np.where(hit, X[0] ^ P, X[0])                 # reflect
+            t = np.where(hit, np.uint64(0), (X[0] ^ X[i]) & P)    # or swap axes 0 and i
+            X[0] = X[0] ^ t
+            X[i] = X[i] ^ t
+        q >>= 1
+    for i in range(1, d):                                         # Gray encode
+        X[i] = X[i] ^ X[i - 1]
+    t = np.zeros(n, dtype=np.uint64)
+    q = 1 << (bits - 1)
+    while q > 1:
+        t = np.where((X[d - 1] & np.uint64(q)) != 0, t ^ np.uint64(q - 1), t)
+        q >>= 1
+    for i in range(d):
+        X[i] = X[i] ^ t
+    key = np.zeros(n, dtype=np.uint64)
+    for b in range(bits - 1, -1, -1):
+        for i in range(d):
+            key = (key << np.uint64(1)) | ((X[i] >> np.uint64(b)) & np.uint64(1))
+    return key
+
+
+def hilbert_order(cen: np.ndarray) -> np.ndarray:
+    cells, bits = _cells(cen)
+    keys = hilbert_index(cells, bits)
+    return np.lexsort((np.arange(cen.shape[0]), keys))
 
 
 def morton_order(cen: np.ndarray) -> np.ndarray:
@@ -68,7 +122,7 @@ def reorder(locs_perm: np.ndarray, block_ptr: np.ndarray, metric_scale, method: 
     """New block order of blocks already in some order: returns (order, point
     permutation into locs_perm, new block_ptr)."""
     cen = block_centroids(locs_perm, block_ptr, metric_scale)
-    order = {"morton": morton_order, "maxmin": maxmin_order}[method](cen)
+    order = {"morton": morton_order, "maxmin": maxmin_order, "hilbert": hilbert_order}[method](cen)
     sizes = np.diff(block_ptr)[order]
     bp = np.zeros(order.size + 1, dtype=np.int64)
     np.cumsum(sizes, out=bp[1:])

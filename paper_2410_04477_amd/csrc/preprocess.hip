@@ -903,7 +903,8 @@ extern "C" int vecchia_pred_neighbors(const double* locs_obs, int64_t n_obs, con
 }
 
 // ------------------------------------------------------------ block order --
-// Morton and maxmin orderings of the blocks (Section 2.1) by their centroids.
+// Morton, Hilbert and maxmin orderings of the blocks (Section 2.1) by their
+// centroids.
 
 namespace bv {
 
@@ -934,6 +935,51 @@ __global__ void morton_kernel(const double* __restrict__ cen, int bc, int d, dou
   unsigned long long v = 0;
   for (int i = 0; i < bits; ++i)
     for (int k = 0; k < d; ++k) v |= ((cell[k] >> i) & 1ull) << (i * d + k);
+  key[b] = v;
+  idx[b] = b;
+}
+
+// Distance along the Hilbert curve of order B of the same cells (Skilling's
+// transform, AIP Conf. Proc. 707, 2004): walking from the top bit down, the
+// low bits are reflected (axis 0) or swapped between axis 0 and axis i,
+// then Gray-encoded; the index reads the bits level by level, axis 0 most
+// significant within a level.  In 1-D the curve is the cell order.
+__global__ void hilbert_kernel(const double* __restrict__ cen, int bc, int d, double lo0, double lo1, double lo2,
+                               double ex0, double ex1, double ex2, unsigned long long* __restrict__ key,
+                               int64_t* __restrict__ idx) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= bc) return;
+  const int bits = d == 1 ? 63 : (d == 2 ? 32 : 21);
+  const double scale = (double)(1ull << bits);
+  const double lo[3] = {lo0, lo1, lo2}, ex[3] = {ex0, ex1, ex2};
+  unsigned long long X[3] = {0, 0, 0};
+  for (int k = 0; k < d; ++k) {
+    const double t = floor((cen[(size_t)b * d + k] - lo[k]) / ex[k] * scale);
+    X[k] = (unsigned long long)fmin(t, scale - 1.0);
+  }
+  unsigned long long v = X[0];
+  if (d > 1) {
+    for (unsigned long long q = 1ull << (bits - 1); q > 1; q >>= 1) {
+      const unsigned long long p = q - 1;
+      for (int i = 0; i < d; ++i) {
+        if (X[i] & q) {
+          X[0] ^= p;
+        } else {
+          const unsigned long long t = (X[0] ^ X[i]) & p;
+          X[0] ^= t;
+          X[i] ^= t;
+        }
+      }
+    }
+    for (int i = 1; i < d; ++i) X[i] ^= X[i - 1];
+    unsigned long long t = 0;
+    for (unsigned long long q = 1ull << (bits - 1); q > 1; q >>= 1)
+      if (X[d - 1] & q) t ^= q - 1;
+    for (int i = 0; i < d; ++i) X[i] ^= t;
+    v = 0;
+    for (int l = bits - 1; l >= 0; --l)
+      for (int i = 0; i < d; ++i) v = (v << 1) | ((X[i] >> l) & 1ull);
+  }
   key[b] = v;
   idx[b] = b;
 }
@@ -1162,7 +1208,8 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
                                       void* stream) {
   if (!locs_perm || !block_ptr || !block_order || !point_perm || !block_ptr_out || !workspace) return VECCHIA_EINVAL;
   if (n <= 0 || bc <= 0 || bc > n || d < 1 || d > 3 || n >= ((int64_t)1 << 31)) return VECCHIA_EINVAL;
-  if (method != VECCHIA_ORDER_MORTON && method != VECCHIA_ORDER_MAXMIN) return VECCHIA_EINVAL;
+  if (method != VECCHIA_ORDER_MORTON && method != VECCHIA_ORDER_MAXMIN && method != VECCHIA_ORDER_HILBERT)
+    return VECCHIA_EINVAL;
   double w[3];
   if (metric_weights(metric_scale, d, w)) return VECCHIA_EINVAL;
   const OrderLayout L = order_layout(bc, d);
@@ -1174,7 +1221,7 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
                      block_ptr, ib, cen);
   PCHECK(hipGetLastError());
   int64_t* order = block_order;
-  if (method == VECCHIA_ORDER_MORTON) {
+  if (method == VECCHIA_ORDER_MORTON || method == VECCHIA_ORDER_HILBERT) {
     const double one[3] = {1.0, 1.0, 1.0};
     double lo[3], hi[3], ex[3];
     int st = bbox(cen, bc, d, one, at<double>(workspace, L.part), lo, hi, s);
@@ -1182,8 +1229,8 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
     for (int k = 0; k < 3; ++k) ex[k] = (k < d && hi[k] > lo[k]) ? hi[k] - lo[k] : 1.0;
     unsigned long long* key = at<unsigned long long>(workspace, L.key);
     int64_t* idx = at<int64_t>(workspace, L.idx);
-    hipLaunchKernelGGL(morton_kernel, dim3(cdiv64(bc, 256)), dim3(256), 0, s, cen, ib, d, lo[0], lo[1], lo[2], ex[0],
-                       ex[1], ex[2], key, idx);
+    hipLaunchKernelGGL(method == VECCHIA_ORDER_MORTON ? morton_kernel : hilbert_kernel, dim3(cdiv64(bc, 256)),
+                       dim3(256), 0, s, cen, ib, d, lo[0], lo[1], lo[2], ex[0], ex[1], ex[2], key, idx);
     PCHECK(hipGetLastError());
     size_t tmp = L.scan - L.sort;
     // radix sort is stable: equal keys keep the ascending block index

@@ -4,6 +4,8 @@ cell coordinates, checked against a hand-listed 4 x 4 sequence), the maxmin
 order satisfies its defining property by brute force, and reordering keeps
 every block intact; with the KL divergence (eq. (kl-gaussian-vecchia)) the
 orderings are compared as in the paper's ordering study."""
+import itertools
+
 import numpy as np
 import pytest
 
@@ -50,7 +52,7 @@ def test_maxmin_property_brute_force():
         assert mind[order[t]] == pytest.approx(mind.max(), rel=1e-12)
 
 
-@pytest.mark.parametrize("method", ["morton", "maxmin"])
+@pytest.mark.parametrize("method", ["morton", "maxmin", "hilbert"])
 def test_reorder_keeps_blocks(method):
     g = W.rng(202)
     s = g.random((300, 2))
@@ -85,3 +87,30 @@ def test_orderings_kl_properties_small():
             kls.append(OL.kl_divergence(lpo, bpo, nptr, nidx, th))
         assert all(v >= -1e-9 for v in kls)
         assert kls[0] >= kls[1] - 1e-9 and kls[1] >= kls[2] - 1e-9
+
+
+@pytest.mark.parametrize("d,k", [(2, 1), (2, 2), (2, 3), (2, 5), (3, 1), (3, 2), (3, 3)])
+def test_hilbert_index_is_a_hilbert_curve(d, k):
+    """The defining properties of a Hilbert curve on every 2^k grid: the
+    indices of the 2^(kd) cells are a permutation of 0 .. 2^(kd) - 1, the
+    curve starts at the origin, and cells with consecutive indices are
+    neighbours (Manhattan distance 1).  With the full key width (B = 32 in
+    2-D, 21 in 3-D) the first 2^(kd) indices fill the sub-grid at the origin."""
+    pts = np.array(list(itertools.product(range(2 ** k), repeat=d)), dtype=np.uint64)
+    for bits in (k, {2: 32, 3: 21}[d]):
+        key = O.hilbert_index(pts, bits)
+        assert np.array_equal(np.sort(key), np.arange(2 ** (k * d), dtype=np.uint64))
+        c = pts[np.argsort(key)].astype(np.int64)
+        assert not c[0].any()
+        assert np.all(np.abs(np.diff(c, axis=0)).sum(1) == 1)
+
+
+def test_hilbert_order_1d_and_locality():
+    """1-D: the cell order.  2-D: blocks adjacent in the Hilbert order are on
+    average closer than under a random order (locality of the curve)."""
+    g = W.rng(204)
+    x = g.random((50, 1))
+    assert np.array_equal(O.hilbert_order(x), np.lexsort((np.arange(50), x[:, 0])))
+    c = g.random((400, 2))
+    steps = lambda o: np.linalg.norm(np.diff(c[o], axis=0), axis=1).mean()
+    assert steps(O.hilbert_order(c)) < 0.25 * steps(g.permutation(400))
