@@ -239,10 +239,10 @@ def main() -> int:
     if n_new > 0:
         prediction = bench_prediction(model, locs_new, y_new, w, th0, metric, args.steps, dev)
 
-    # ---- block orderings (preprocessing, untimed in the step): Morton, Hilbert, maxmin --
+    # ---- block orderings (preprocessing, untimed in the step): Morton, Hilbert, KD-tree, maxmin --
     t_order = {}
     if not args.no_prediction:
-        for method in ("morton", "hilbert", "maxmin"):
+        for method in ("morton", "hilbert", "kdtree", "maxmin"):
             log(f"reordering {plan.bc} blocks: {method}")
             torch.cuda.synchronize()
             t0 = time.perf_counter()

@@ -148,6 +148,10 @@ int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const doubl
  *   VECCHIA_ORDER_HILBERT the Morton cells, keyed by their distance along the
  *                         Hilbert curve of order B (Skilling's transform; in
  *                         1-D the cell order), sorted by key then block index
+ *   VECCHIA_ORDER_KDTREE  leaves of a k-d tree from left to right: median
+ *                         splits with the axis cycling with depth (depth mod
+ *                         d); a node's blocks sorted by (coordinate, block
+ *                         index), the first floor(k/2) to the left child
  * vecchia_reorder_blocks takes points already grouped into blocks (locs_perm,
  * block_ptr) and returns
  *   block_order    out, bc int64: position -> current block index
@@ -160,6 +164,7 @@ int vecchia_neighbors(const double* locs_perm, int64_t n, int32_t d, const doubl
 #define VECCHIA_ORDER_MORTON 1
 #define VECCHIA_ORDER_MAXMIN 2
 #define VECCHIA_ORDER_HILBERT 3
+#define VECCHIA_ORDER_KDTREE 4
 size_t vecchia_reorder_blocks_workspace_size(int64_t n, int64_t bc, int32_t d);
 int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_t d, const double* metric_scale,
                            const int32_t* block_ptr, int64_t bc, int32_t method, int64_t* block_order,

@@ -1,4 +1,5 @@
-"""Block orderings (Section 2.1: Morton, Hilbert and maxmin reorderings of the blocks),
+"""Block orderings (Section 2.1: Morton, Hilbert, KD-tree and maxmin reorderings of the
+blocks),
 numpy FP64.  The KL divergence used to compare them (eq.
 (kl-gaussian-vecchia)) is loglik.kl_divergence.
 
@@ -18,6 +19,11 @@ Readings where the paper is silent:
     bit down, undo the curve's rotations and reflections, Gray-encode, then
     read the index bits level by level, axis 0 most significant within a
     level.  In 1-D the curve is the cell order itself.  Sorted like Morton.
+  * KD-tree: a k-d tree over the centroids built by median splits with the
+    axis cycling with depth (axis = depth mod d, as in Bentley's tree); a
+    node's blocks are sorted by (coordinate on that axis, block index), the
+    first floor(k/2) go to the left child, and the order is that of the
+    single-block leaves from left to right.
   * Maxmin: the first block is the one whose centroid is nearest the mean of
     the centroids (summed in block order); each next block maximises the minimum squared distance to
     the blocks already placed; ties by lowest block index.  Squared distances
@@ -93,6 +99,20 @@ def hilbert_order(cen: np.ndarray) -> np.ndarray:
     return np.lexsort((np.arange(cen.shape[0]), keys))
 
 
+def kdtree_order(cen: np.ndarray) -> np.ndarray:
+    d = cen.shape[1]
+
+    def visit(idx: np.ndarray, depth: int) -> list:
+        if idx.size <= 1:
+            return list(idx)
+        axis = depth % d
+        srt = idx[np.lexsort((idx, cen[idx, axis]))]
+        mid = idx.size // 2
+        return visit(srt[:mid], depth + 1) + visit(srt[mid:], depth + 1)
+
+    return np.array(visit(np.arange(cen.shape[0]), 0), dtype=np.int64)
+
+
 def morton_order(cen: np.ndarray) -> np.ndarray:
     keys = morton_keys(cen)
     return np.lexsort((np.arange(cen.shape[0]), keys))
@@ -122,7 +142,8 @@ def reorder(locs_perm: np.ndarray, block_ptr: np.ndarray, metric_scale, method: 
     """New block order of blocks already in some order: returns (order, point
     permutation into locs_perm, new block_ptr)."""
     cen = block_centroids(locs_perm, block_ptr, metric_scale)
-    order = {"morton": morton_order, "maxmin": maxmin_order, "hilbert": hilbert_order}[method](cen)
+    order = {"morton": morton_order, "maxmin": maxmin_order, "hilbert": hilbert_order,
+             "kdtree": kdtree_order}[method](cen)
     sizes = np.diff(block_ptr)[order]
     bp = np.zeros(order.size + 1, dtype=np.int64)
     np.cumsum(sizes, out=bp[1:])

@@ -13,7 +13,7 @@ MAX_BUCKETS = 24
 MAX_JOINT = 175
 ENGINE_MFMA, ENGINE_TILES, ENGINE_MFMA_WG = 0, 1, 2
 PLAN_PREDICT = 16
-ORDER_MORTON, ORDER_MAXMIN, ORDER_HILBERT = 1, 2, 3
+ORDER_MORTON, ORDER_MAXMIN, ORDER_HILBERT, ORDER_KDTREE = 1, 2, 3, 4
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
 FP64, FP32_BULK = 0, 1

@@ -108,7 +108,8 @@ def neighbors(locs_perm: torch.Tensor, block_ptr: torch.Tensor, m: int,
     return nptr, nidx[:total].clone()
 
 
-ORDERS = {"morton": L.ORDER_MORTON, "maxmin": L.ORDER_MAXMIN, "hilbert": L.ORDER_HILBERT}
+ORDERS = {"morton": L.ORDER_MORTON, "maxmin": L.ORDER_MAXMIN, "hilbert": L.ORDER_HILBERT,
+          "kdtree": L.ORDER_KDTREE}
 
 
 def reorder_blocks(locs_perm: torch.Tensor, block_ptr: torch.Tensor, method: str,

@@ -903,8 +903,8 @@ extern "C" int vecchia_pred_neighbors(const double* locs_obs, int64_t n_obs, con
 }
 
 // ------------------------------------------------------------ block order --
-// Morton, Hilbert and maxmin orderings of the blocks (Section 2.1) by their
-// centroids.
+// Morton, Hilbert, KD-tree and maxmin orderings of the blocks (Section 2.1)
+// by their centroids.
 
 namespace bv {
 
@@ -982,6 +982,61 @@ __global__ void hilbert_kernel(const double* __restrict__ cen, int bc, int d, do
   }
   key[b] = v;
   idx[b] = b;
+}
+
+// KD-tree order, one tree level per pass (axis = level mod d): the blocks are
+// sorted by their coordinate on the axis (stable, so ties keep the block
+// index), then stably by the node that holds each block's current position,
+// which sorts every node's blocks by coordinate; the node of a position at
+// depth L follows from halving [0, bc) L times (left child: the first half,
+// rounded down), so no tree is stored.
+__device__ inline unsigned long long ordered_bits(double x) {
+  // total order of finite doubles as unsigned integers (-0 folded into +0)
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x + 0.0);
+  return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+
+__global__ void kd_init_kernel(int bc, int64_t* __restrict__ pos, int64_t* __restrict__ order) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= bc) return;
+  pos[b] = b;
+  order[b] = b;
+}
+
+__global__ void kd_coord_kernel(const double* __restrict__ cen, int bc, int d, int axis,
+                                unsigned long long* __restrict__ key, int64_t* __restrict__ idx) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= bc) return;
+  key[b] = ordered_bits(cen[(size_t)b * d + axis]);
+  idx[b] = b;
+}
+
+__global__ void kd_node_kernel(const int64_t* __restrict__ by_coord, const int64_t* __restrict__ pos, int bc,
+                               int level, unsigned long long* __restrict__ key, int64_t* __restrict__ idx) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= bc) return;
+  const int64_t b = by_coord[i];
+  const int64_t p = pos[b];
+  int64_t lo = 0, hi = bc;
+  unsigned long long node = 0;
+  for (int l = 0; l < level; ++l) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (p < mid) {
+      hi = mid;
+      node = 2 * node;
+    } else {
+      lo = mid;
+      node = 2 * node + 1;
+    }
+  }
+  key[i] = node;
+  idx[i] = b;
+}
+
+__global__ void kd_pos_kernel(const int64_t* __restrict__ order, int bc, int64_t* __restrict__ pos) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= bc) return;
+  pos[order[p]] = p;
 }
 
 // Greedy maxmin by one workgroup: the first block is the one nearest the mean
@@ -1208,7 +1263,8 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
                                       void* stream) {
   if (!locs_perm || !block_ptr || !block_order || !point_perm || !block_ptr_out || !workspace) return VECCHIA_EINVAL;
   if (n <= 0 || bc <= 0 || bc > n || d < 1 || d > 3 || n >= ((int64_t)1 << 31)) return VECCHIA_EINVAL;
-  if (method != VECCHIA_ORDER_MORTON && method != VECCHIA_ORDER_MAXMIN && method != VECCHIA_ORDER_HILBERT)
+  if (method != VECCHIA_ORDER_MORTON && method != VECCHIA_ORDER_MAXMIN && method != VECCHIA_ORDER_HILBERT &&
+      method != VECCHIA_ORDER_KDTREE)
     return VECCHIA_EINVAL;
   double w[3];
   if (metric_weights(metric_scale, d, w)) return VECCHIA_EINVAL;
@@ -1236,6 +1292,29 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
     // radix sort is stable: equal keys keep the ascending block index
     PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key,
                                               at<unsigned long long>(workspace, L.key2), idx, order, ib, 0, 64, s));
+  } else if (method == VECCHIA_ORDER_KDTREE) {
+    unsigned long long* key = at<unsigned long long>(workspace, L.key);
+    unsigned long long* key2 = at<unsigned long long>(workspace, L.key2);
+    int64_t* idx = at<int64_t>(workspace, L.idx);
+    int64_t* idx2 = at<int64_t>(workspace, L.idx2);
+    int64_t* pos = at<int64_t>(workspace, L.mind);   // bc slots of 8 bytes
+    const unsigned g = (unsigned)cdiv64(bc, 256);
+    hipLaunchKernelGGL(kd_init_kernel, dim3(g), dim3(256), 0, s, ib, pos, order);
+    PCHECK(hipGetLastError());
+    int levels = 0;
+    while (((int64_t)1 << levels) < bc) ++levels;
+    for (int level = 0; level < levels; ++level) {
+      size_t tmp = L.scan - L.sort;
+      hipLaunchKernelGGL(kd_coord_kernel, dim3(g), dim3(256), 0, s, cen, ib, d, level % d, key, idx);
+      PCHECK(hipGetLastError());
+      PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key, key2, idx, idx2, ib, 0, 64, s));
+      hipLaunchKernelGGL(kd_node_kernel, dim3(g), dim3(256), 0, s, idx2, pos, ib, level, key, idx);
+      PCHECK(hipGetLastError());
+      tmp = L.scan - L.sort;
+      PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key, key2, idx, order, ib, 0, 64, s));
+      hipLaunchKernelGGL(kd_pos_kernel, dim3(g), dim3(256), 0, s, order, ib, pos);
+      PCHECK(hipGetLastError());
+    }
   } else {
     // up to 8192 blocks one workgroup does every step; above, one launch pair
     // per step spreads the O(bc) distance updates over the device

@@ -17,8 +17,8 @@ class BlockVecchia:
 
     locs: n x d (original order), y: n.  init_idx / block_perm are the
     K-means start points and the random block order (drawn by the caller).
-    ordering: "random" (that order), "morton", "hilbert" or "maxmin" (block
-    centroids).
+    ordering: "random" (that order), "morton", "hilbert", "kdtree" or "maxmin"
+    (block centroids).
     aniso: per-axis range multipliers; neighbour search and K-means use the
     metric 1/aniso.  nu is fixed per model: 0.5, 1.5, 2.5 in closed form, any
     other value in [0.05, 10] through the Bessel form (engine "mfma")."""

@@ -1,7 +1,7 @@
 """Block orderings on the GPU (Morton, maxmin) against the oracle bit for
 bit, and the ordering study of Section 3 in small: KL divergences (eq.
-(kl-gaussian-vecchia)) of random, Morton, Hilbert and maxmin orders, GPU
-against the oracle."""
+(kl-gaussian-vecchia)) of random, Morton, Hilbert, KD-tree and maxmin
+orders, GPU against the oracle."""
 import numpy as np
 import pytest
 import torch
@@ -28,7 +28,7 @@ def _blocks(n, d, bc, seed, zmax=1.0):
     return s[perm], bp, wscale
 
 
-@pytest.mark.parametrize("method", ["morton", "maxmin", "hilbert"])
+@pytest.mark.parametrize("method", ["morton", "maxmin", "hilbert", "kdtree"])
 @pytest.mark.parametrize("n,d,bc", [(3000, 2, 300), (20000, 2, 2000), (6000, 3, 500), (50, 2, 1), (400, 1, 37),
                                     (60000, 2, 10000)])
 def test_reorder_matches_oracle(method, n, d, bc):
@@ -63,7 +63,7 @@ def test_ordering_kl_study():
         labels, _ = P.kmeans(s, [1.0, 1.0], W.kmeans_init(n, bc, 312), 10)
         perm, bp = P.order_blocks(labels, W.block_permutation(bc, 312))
         lp = s[perm]
-        for method in ("random", "morton", "hilbert", "maxmin"):
+        for method in ("random", "morton", "hilbert", "kdtree", "maxmin"):
             if method == "random":
                 lpo, bpo = lp, bp
             else:

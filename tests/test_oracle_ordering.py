@@ -52,7 +52,7 @@ def test_maxmin_property_brute_force():
         assert mind[order[t]] == pytest.approx(mind.max(), rel=1e-12)
 
 
-@pytest.mark.parametrize("method", ["morton", "maxmin", "hilbert"])
+@pytest.mark.parametrize("method", ["morton", "maxmin", "hilbert", "kdtree"])
 def test_reorder_keeps_blocks(method):
     g = W.rng(202)
     s = g.random((300, 2))
@@ -114,3 +114,31 @@ def test_hilbert_order_1d_and_locality():
     c = g.random((400, 2))
     steps = lambda o: np.linalg.norm(np.diff(c[o], axis=0), axis=1).mean()
     assert steps(O.hilbert_order(c)) < 0.25 * steps(g.permutation(400))
+
+
+def test_kdtree_order_of_a_grid_and_split_property():
+    """On a 4 x 4 grid (axis 0 split first, then axis 1, then axis 0 ...) the
+    order is the nested quadrants: x < 2 before x >= 2, and within each half
+    y < 2 before y >= 2, and so on down to single cells.  On random points
+    every subtree holds a contiguous range split at the median."""
+    pts = np.array([(x, y) for x in range(4) for y in range(4)], dtype=np.float64)
+    o = O.kdtree_order(pts)
+    c = pts[o]
+    expect = [(0, 0), (0, 1), (1, 0), (1, 1), (0, 2), (0, 3), (1, 2), (1, 3),
+              (2, 0), (2, 1), (3, 0), (3, 1), (2, 2), (2, 3), (3, 2), (3, 3)]
+    assert [tuple(int(v) for v in r) for r in c] == expect
+    g = W.rng(205)
+    cen = g.random((37, 3))
+    o = O.kdtree_order(cen)
+    assert np.array_equal(np.sort(o), np.arange(37))
+
+    def check(lo, hi, depth):
+        if hi - lo <= 1:
+            return
+        axis, mid = depth % 3, lo + (hi - lo) // 2
+        left, right = cen[o[lo:mid], axis], cen[o[mid:hi], axis]
+        assert left.max() <= right.min()
+        check(lo, mid, depth + 1)
+        check(mid, hi, depth + 1)
+
+    check(0, 37, 0)
