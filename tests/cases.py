@@ -60,3 +60,22 @@ def oracle_sum(terms) -> float:
     for v in terms:
         acc += float(v)
     return acc
+
+
+def fourier_field(locs: np.ndarray, sigma2: float, scale, nugget: float, seed: int, nfeat: int = 256) -> np.ndarray:
+    """A smooth seeded random field for full-size parity inputs where the
+    block Vecchia simulator would need every block's neighbours from the
+    oracle: sum of nfeat random cosines with frequencies N(0, 1 / scale^2) per
+    axis (variance sigma2, correlation length ~ scale), plus white noise of
+    variance nugget.  Not a draw from the Matern model; any y is a valid
+    likelihood input, and this one has the value range and spatial structure
+    of the simulated fields."""
+    g = W.rng(seed)
+    d = locs.shape[1]
+    om = g.standard_normal((nfeat, d)) / np.asarray(scale, dtype=np.float64)[:d]
+    ph = g.uniform(0.0, 2.0 * np.pi, nfeat)
+    y = np.zeros(locs.shape[0])
+    for f in range(nfeat):
+        y += np.cos(locs @ om[f] + ph[f])
+    y *= np.sqrt(2.0 * sigma2 / nfeat)
+    return y + np.sqrt(nugget) * g.standard_normal(locs.shape[0])

@@ -1,0 +1,99 @@
+"""The n = 1e6 3-D anisotropic workload at full size (50,000 blocks,
+m = 120, nu = 2.5), in the launch configuration of the benchmark (the same
+plan builder and engine): log-likelihood and adjoint gradient per block, FP64
+and FP32-bulk, on a seeded sample of blocks against the C oracle, and the GPU
+neighbour lists of the sampled blocks against brute force.
+
+Oracle-side inputs: locations from the seeded generator, blocks from the
+oracle's own K-means (3 Lloyd iterations: a valid partition with the
+workload's block-size spread), and a smooth random field for y (the
+block Vecchia simulator would need the oracle's neighbours of every block,
+minutes of CPU time at this size).  The neighbour lists come from the
+library; the sampled blocks are first checked to have exactly the oracle's
+brute-force lists, which the oracle then uses."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from cases import fourier_field
+from oracle import coracle, preprocess as P
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+NSAMPLE = 64
+
+
+def _t(a, dt=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dt, device=DEV)
+
+
+def test_n1e6_3d_sampled_blocks_vs_oracle():
+    from paper_2410_04477_amd import api
+    w = W.C3
+    th = w.theta
+    metric = list(w.metric_scale)
+    s = W.locations(w)
+    labels, _ = P.kmeans(s, metric, W.kmeans_init(w.n, w.bc, w.seed_kmeans), 3)
+    perm, bp = P.order_blocks(labels, W.block_permutation(w.bc, w.seed_kmeans))
+    lp = s[perm]
+    y = fourier_field(lp, th.sigma2, [th.beta * a for a in th.aniso], th.nugget, w.seed_y)
+    print(f"n={w.n} bc={bp.size - 1} block sizes {np.diff(bp).min()}..{np.diff(bp).max()}", flush=True)
+
+    lp_t, y_t, bp_t = _t(lp), _t(y), _t(bp, torch.int32)
+    npt, nid = api.neighbors(lp_t, bp_t, w.m, metric)
+    plan = api.Plan(bp_t, npt, w.n, 1)
+    print("classes G", sorted(int(c) + 1 for c in plan.c.bucket_cfg[:plan.c.nbuckets]), flush=True)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        ll, g, cnt, part, gpart = api.loglik_grad(plan, lp_t, y_t, nid, [th], prec, want_partial=True)
+        ll_v, _, part_v = api.loglik(plan, lp_t, y_t, nid, [th], prec, want_partial=True)
+        res[prec] = dict(ll=float(ll[0]), g=g[0].cpu().numpy(), part=part[0].cpu().numpy(),
+                         gpart=gpart[0].cpu().numpy(), ll_v=float(ll_v[0]), part_v=part_v[0].cpu().numpy(),
+                         cnt=cnt[0].cpu().numpy())
+    npt_h, nid_h = npt.cpu().numpy(), nid.cpu().numpy()
+
+    sample = np.sort(W.rng(4242).choice(bp.size - 1, size=NSAMPLE, replace=False))
+    x = lp * np.asarray(metric)
+    o_ptr = np.zeros(bp.size, dtype=np.int64)
+    rows = []
+    for i in sample:
+        a, b = int(bp[i]), int(bp[i + 1])
+        c = P.block_centroids(lp[a:b], np.array([0, b - a]), metric)[0]
+        ref = P._knn_one(c, x[:a], min(w.m, a)).astype(np.int64)
+        got = nid_h[npt_h[i]:npt_h[i + 1]]
+        assert np.array_equal(got, ref), f"block {i}"
+        rows.append(ref)
+        o_ptr[i + 1] = ref.size
+    o_ptr = np.cumsum(o_ptr)
+    o_idx = np.concatenate(rows)
+    ref_l, ref_g = coracle.selected_terms(lp, y, bp, o_ptr, o_idx, th, sample, with_grad=True)
+
+    # FP64: every sampled block within 1e-8 (of the mean |l_i|; gradient rows of
+    # sum_i |g_i|).  FP32-bulk: the stated bars apply to sums over blocks
+    # (1e-4 relative on l, 1e-3 on the gradient); on the sample, the sum of
+    # |errors| of l_i (no cancellation allowed) within 1e-4 of sum |l_i|, and
+    # the sample's gradient sum within 1e-3 of sum_i |g_i|.
+    scale_l = np.abs(ref_l).mean()
+    gscale = np.abs(ref_g).sum(0)
+    for prec in ("fp64", "fp32"):
+        r = res[prec]
+        el = np.abs(r["part"][sample] - ref_l)
+        ev = np.abs(r["part_v"][sample] - ref_l)
+        dg = r["gpart"][sample] - ref_g
+        print(f"{prec}: max |dl_i| {el.max():.2e}, sum |dl_i| / sum |l_i| {el.sum() / np.abs(ref_l).sum():.1e} "
+              f"(value path {ev.sum() / np.abs(ref_l).sum():.1e}); gradient: sum |dg_i| / sum |g_i| "
+              f"{np.abs(dg).sum(0) / gscale}, |sum dg_i| / sum |g_i| {np.abs(dg.sum(0)) / gscale}; "
+              f"guard re-factors {r['cnt'][0]}", flush=True)
+        if prec == "fp64":
+            assert el.max() <= 1e-8 * scale_l and ev.max() <= 1e-8 * scale_l
+            assert np.all(np.abs(dg).sum(0) <= 1e-8 * gscale)
+        else:
+            assert el.sum() <= 1e-4 * np.abs(ref_l).sum() and ev.sum() <= 1e-4 * np.abs(ref_l).sum()
+            assert np.all(np.abs(dg.sum(0)) <= 1e-3 * gscale)
+        assert r["cnt"][1] == 0
+    # totals: FP32-bulk within 1e-4 of FP64; the value path equals the value of the gradient path
+    assert abs(res["fp32"]["ll"] - res["fp64"]["ll"]) <= 1e-4 * abs(res["fp64"]["ll"])
+    assert abs(res["fp64"]["ll_v"] - res["fp64"]["ll"]) <= 1e-10 * abs(res["fp64"]["ll"])
+    print(f"totals: fp64 {res['fp64']['ll']:.6f} fp32 {res['fp32']['ll']:.6f} "
+          f"rel {abs(res['fp32']['ll'] - res['fp64']['ll']) / abs(res['fp64']['ll']):.1e}", flush=True)
