@@ -58,6 +58,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="C3")
     ap.add_argument("--engine", default="mfma", choices=["mfma", "mfma_wg", "tiles"])
+    ap.add_argument("--scale", type=int, default=1,
+                    help="multiply the workload's n and block count (same points per block and m)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
@@ -81,6 +83,8 @@ def main() -> int:
     from paper_2410_04477_amd.model import BlockVecchia
 
     w = W.WORKLOADS[args.workload]
+    if args.scale != 1:
+        w = W.scaled(w, w.n * args.scale, tag=f"x{args.scale}")
     dev = torch.device("cuda:0")
     th0 = w.theta
     t_setup = time.perf_counter()
@@ -184,7 +188,9 @@ def main() -> int:
     if os.path.exists(tpath):
         with open(tpath) as fh:
             tr = json.load(fh)
-        if tr.get("kernel_source_sha") == kernel_source_sha() and all(n in tr for n in names):
+        # the counters were taken on the default workload: other sizes report none
+        if (args.workload == "C3" and args.scale == 1 and tr.get("kernel_source_sha") == kernel_source_sha()
+                and all(n in tr for n in names)):
             traffic = float(sum(tr[n]["bytes_per_launch"] for n in names))
     roofline = {"bound": "alu" if plan.engine == "tiles" else "mfma", "achieved": achieved / 1e12,
                 "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
