@@ -130,6 +130,104 @@ __global__ void __launch_bounds__(256) km_assign_kernel(KmArgs a, int first) {
   }
 }
 
+// Large block counts: a uniform grid of cubic cells (side h, in the scaled
+// coordinates, over the points' bounding box) holds the centroids, about two
+// per cell, and each point searches rings of cells around its own until the
+// next ring is farther than the best distance found.  A centroid in a cell r+1
+// rings away is at least r h from the point, so the search is exact; ties go
+// to the lowest centroid index, as in the exhaustive kernel.
+constexpr int64_t kKmGridMinBlocks = 65536;
+
+struct KmGrid {
+  double lo[3];
+  double h, inv_h;
+  int nc[3];
+  int ncell;
+  int* cstart;   // ncell + 1 (exclusive scan of the counts)
+  int* ccur;     // ncell + 1: counts, then insertion cursors
+  int* cidx;     // bc centroid indices grouped by cell
+};
+
+__device__ inline int km_grid_cell(const KmGrid& g, const double* x, int d, int* pc) {
+  int cell = 0, stride = 1;
+  for (int k = 0; k < 3; ++k) {
+    int c = 0;
+    if (k < d) {
+      const double t = floor((x[k] - g.lo[k]) * g.inv_h);
+      c = !(t >= 0.0) ? 0 : (t >= (double)g.nc[k] ? g.nc[k] - 1 : (int)t);
+    }
+    pc[k] = c;
+    cell += c * stride;
+    stride *= g.nc[k];
+  }
+  return cell;
+}
+
+__global__ void km_grid_count_kernel(KmArgs a, KmGrid g) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.bc) return;
+  int pc[3];
+  atomicAdd(&g.ccur[km_grid_cell(g, a.cent + (size_t)c * 3, a.d, pc)], 1);
+}
+
+__global__ void km_grid_cursor_kernel(KmGrid g) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i <= g.ncell) g.ccur[i] = g.cstart[i];
+}
+
+__global__ void km_grid_place_kernel(KmArgs a, KmGrid g) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.bc) return;
+  int pc[3];
+  const int pos = atomicAdd(&g.ccur[km_grid_cell(g, a.cent + (size_t)c * 3, a.d, pc)], 1);
+  g.cidx[pos] = c;
+}
+
+__global__ void __launch_bounds__(256) km_assign_grid_kernel(KmArgs a, KmGrid g, int first) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= a.n) return;
+  double x[3] = {0, 0, 0};
+  for (int k = 0; k < a.d; ++k) x[k] = a.locs[i * a.d + k] * a.w[k];
+  int pc[3];
+  km_grid_cell(g, x, a.d, pc);
+  const int rmax = max(g.nc[0], max(g.nc[1], g.nc[2]));
+  double best = INFINITY;
+  int bi = 0x7fffffff;
+  for (int r = 0; r <= rmax; ++r) {
+    const int r1 = a.d > 1 ? r : 0, r2 = a.d > 2 ? r : 0;
+    for (int o2 = -r2; o2 <= r2; ++o2) {
+      const int c2 = pc[2] + o2;
+      if (c2 < 0 || c2 >= g.nc[2]) continue;
+      for (int o1 = -r1; o1 <= r1; ++o1) {
+        const int c1 = pc[1] + o1;
+        if (c1 < 0 || c1 >= g.nc[1]) continue;
+        for (int o0 = -r; o0 <= r; ++o0) {
+          const int c0 = pc[0] + o0;
+          if (c0 < 0 || c0 >= g.nc[0]) continue;
+          if (max(abs(o0), max(abs(o1), abs(o2))) != r) continue;   // this ring only
+          const int cell = c0 + g.nc[0] * (c1 + g.nc[1] * c2);
+          const int q1 = g.cstart[cell + 1];
+          for (int q = g.cstart[cell]; q < q1; ++q) {
+            const int c = g.cidx[q];
+            const double t0 = x[0] - a.cent[c * 3], t1 = x[1] - a.cent[c * 3 + 1], t2 = x[2] - a.cent[c * 3 + 2];
+            const double dd = t0 * t0 + t1 * t1 + t2 * t2;
+            if (dd < best || (dd == best && c < bi)) {
+              best = dd;
+              bi = c;
+            }
+          }
+        }
+      }
+    }
+    const double reach = (double)r * g.h;
+    if (reach * reach * (1.0 - 1e-9) > best) break;
+  }
+  if (!first && a.label[i] != bi) atomicOr(a.changed, 1);
+  a.label[i] = bi;
+  a.dist[i] = best;
+}
+
 __global__ void km_zero_kernel(KmArgs a) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= a.bc) return;
@@ -504,6 +602,8 @@ size_t sort_temp_bytes_i32_i32(int64_t n, int nbits = 32) {
 
 struct BlocksLayout {
   size_t cent, label, fsum, cnt, dist, changed, key, val, key2, val2, pol, kcnt, part, parti, sort, total;
+  size_t gstart, gcur, gidx, gscan;   // centroid grid (large block counts only)
+  int64_t gcells;                     // cell capacity of the grid
 };
 BlocksLayout blocks_layout(int64_t n, int64_t bc) {
   BlocksLayout L;
@@ -523,8 +623,80 @@ BlocksLayout blocks_layout(int64_t n, int64_t bc) {
   L.part = o;    o = al256(o + sizeof(double) * 6 * 1024);
   L.parti = o;   o = al256(o + sizeof(int64_t) * 1024);
   L.sort = o;    o = al256(o + sort_temp_bytes_i32_i64(n));
+  L.gcells = 0;
+  L.gstart = L.gcur = L.gidx = L.gscan = o;
+  if (bc >= kKmGridMinBlocks) {
+    L.gcells = 2 * bc + 64;
+    L.gstart = o; o = al256(o + sizeof(int) * (L.gcells + 1));
+    L.gcur = o;   o = al256(o + sizeof(int) * (L.gcells + 1));
+    L.gidx = o;   o = al256(o + sizeof(int) * bc);
+    size_t sc = 0;
+    hipcub::DeviceScan::ExclusiveSum((void*)nullptr, sc, (const int*)nullptr, (int*)nullptr, (int)(L.gcells + 1),
+                                     (hipStream_t)0);
+    L.gscan = o;  o = al256(o + sc);
+  }
   L.total = o;
   return L;
+}
+
+// Centroid grid for vecchia_blocks: cubic cells of side h over the scaled
+// bounding box [lo, hi], about two centroids per cell, at most L.gcells cells.
+void km_grid_setup(const BlocksLayout& L, void* ws, int64_t bc, int d, const double* lo, const double* hi, KmGrid& g) {
+  memset(&g, 0, sizeof(g));
+  double ext[3] = {0, 0, 0}, vol = 1.0;
+  int deff = 0;
+  for (int k = 0; k < 3; ++k) {
+    g.lo[k] = k < d ? lo[k] : 0.0;
+    ext[k] = k < d ? hi[k] - lo[k] : 0.0;
+    if (ext[k] > 0) {
+      vol *= ext[k];
+      ++deff;
+    }
+  }
+  const double target = std::max(1.0, (double)bc / 2.0);
+  double h = deff ? std::pow(vol / target, 1.0 / deff) : 1.0;
+  if (!(h > 0) || !std::isfinite(h)) h = 1.0;
+  for (;;) {
+    int64_t total = 1;
+    for (int k = 0; k < 3; ++k) {
+      const double c = ext[k] > 0 ? std::ceil(ext[k] / h) : 1.0;
+      g.nc[k] = (int)std::max(1.0, std::min(c, 1e9));
+      total *= g.nc[k];
+      if (total > L.gcells) break;
+    }
+    if (total <= L.gcells) {
+      g.ncell = (int)total;
+      break;
+    }
+    h *= 1.03;   // coarsen until the cell count fits
+  }
+  g.h = h;
+  g.inv_h = 1.0 / h;
+  g.cstart = at<int>(ws, L.gstart);
+  g.ccur = at<int>(ws, L.gcur);
+  g.cidx = at<int>(ws, L.gidx);
+}
+
+// nearest centroid of every point: exhaustive for small block counts, through
+// the centroid grid (rebuilt from the current centroids) for large ones
+int km_assign(const KmArgs& a, const BlocksLayout& L, void* ws, const KmGrid* g, int first, hipStream_t s) {
+  const int gn = cdiv64(a.n, 256);
+  if (!g) {
+    hipLaunchKernelGGL(km_assign_kernel, dim3(gn), dim3(256), 0, s, a, first);
+    PCHECK(hipGetLastError());
+    return VECCHIA_OK;
+  }
+  const int gb = cdiv64(a.bc, 256);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(cdiv64(g->ncell + 1, 256)), dim3(256), 0, s, g->ccur, g->ncell + 1, 0);
+  hipLaunchKernelGGL(km_grid_count_kernel, dim3(gb), dim3(256), 0, s, a, *g);
+  PCHECK(hipGetLastError());
+  size_t tmp = L.total - L.gscan;
+  PCHECK(hipcub::DeviceScan::ExclusiveSum(at<void>(ws, L.gscan), tmp, g->ccur, g->cstart, g->ncell + 1, s));
+  hipLaunchKernelGGL(km_grid_cursor_kernel, dim3(cdiv64(g->ncell + 1, 256)), dim3(256), 0, s, *g);
+  hipLaunchKernelGGL(km_grid_place_kernel, dim3(gb), dim3(256), 0, s, a, *g);
+  hipLaunchKernelGGL(km_assign_grid_kernel, dim3(gn), dim3(256), 0, s, a, *g, first);
+  PCHECK(hipGetLastError());
+  return VECCHIA_OK;
 }
 
 int bbox(const double* locs, int64_t n, int d, const double* w, double* part, double* lo, double* hi, hipStream_t s) {
@@ -602,9 +774,16 @@ extern "C" int vecchia_blocks(const double* locs, int64_t n, int32_t d, const do
   a.cnt = at<int>(workspace, L.cnt);
   a.dist = at<double>(workspace, L.dist);
   const int gb = cdiv64(bc, 256), gn = cdiv64(n, 256);
+  KmGrid grid;
+  const KmGrid* gp = nullptr;
+  if (L.gcells > 0) {
+    km_grid_setup(L, workspace, bc, d, lo, hi, grid);
+    gp = &grid;
+  }
   hipLaunchKernelGGL(km_init_kernel, dim3(gb), dim3(256), 0, s, a, init_idx);
-  hipLaunchKernelGGL(km_assign_kernel, dim3(gn), dim3(256), 0, s, a, 1);
   PCHECK(hipGetLastError());
+  st = km_assign(a, L, workspace, gp, 1, s);
+  if (st) return st;
   int it = 0;
   for (; it < max_iter; ++it) {
     hipLaunchKernelGGL(km_zero_kernel, dim3(gb), dim3(256), 0, s, a);
@@ -644,8 +823,8 @@ extern "C" int vecchia_blocks(const double* locs, int64_t n, int32_t d, const do
       }
     }
     hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, a.changed, 1, 0);
-    hipLaunchKernelGGL(km_assign_kernel, dim3(gn), dim3(256), 0, s, a, 0);
-    PCHECK(hipGetLastError());
+    st = km_assign(a, L, workspace, gp, 0, s);
+    if (st) return st;
     int hch = 0;
     PCHECK(hipMemcpyAsync(&hch, a.changed, sizeof(int), hipMemcpyDeviceToHost, s));
     PCHECK(hipStreamSynchronize(s));

@@ -106,3 +106,44 @@ def test_permute_rows():
     p = torch.tensor(W.point_permutation(1000, 1), device=DEV)
     out = api.permute_rows(s, p)
     assert torch.equal(out, s[p])
+
+
+@pytest.mark.parametrize("n,d,bc", [(300_000, 2, 70_000), (300_000, 3, 80_000)])
+def test_blocks_grid_assignment_large_block_count(n, d, bc):
+    """From 65,536 blocks up, K-means assigns points through a grid over the
+    centroids.  With no Lloyd iteration the blocks are the cells of the
+    initial centroids, checked point by point against a KD-tree; with 30
+    iterations the partition stays valid and the inertia falls."""
+    from scipy.spatial import cKDTree
+    from paper_2410_04477_amd import api
+    s = W.rng(17).random((n, d))
+    if d == 3:
+        s[:, 2] *= 0.2
+    w = [1.0, 1.0, 5.0][:d]
+    x = s * w
+    init = W.kmeans_init(n, bc, 17)
+    bperm = W.block_permutation(bc, 17)
+    args = (torch.tensor(s, device=DEV), bc, torch.tensor(init, device=DEV), torch.tensor(bperm, device=DEV), w)
+    perm, bp, _ = api.blocks(*args, max_iter=0)
+    perm, bp = perm.cpu().numpy(), bp.cpu().numpy()
+    assert sorted(perm.tolist()) == list(range(n))
+    cluster = np.empty(n, dtype=np.int64)
+    for i in range(bc):
+        cluster[perm[bp[i]:bp[i + 1]]] = bperm[i]
+    _, nearest = cKDTree(x[init]).query(x, k=1)
+    assert np.array_equal(cluster, nearest)
+    inert0 = ((x - x[init][cluster]) ** 2).sum()
+
+    perm, bp, iters = api.blocks(*args, max_iter=30)
+    perm, bp = perm.cpu().numpy(), bp.cpu().numpy()
+    assert sorted(perm.tolist()) == list(range(n))
+    assert bp[0] == 0 and bp[-1] == n and np.all(np.diff(bp) > 0)
+    lab = np.empty(n, dtype=np.int64)
+    for i in range(bc):
+        lab[perm[bp[i]:bp[i + 1]]] = i
+    cen = np.zeros((bc, d))
+    np.add.at(cen, lab, x)
+    cen /= np.bincount(lab, minlength=bc)[:, None]
+    inert = ((x - cen[lab]) ** 2).sum()
+    print(f"n={n} d={d} bc={bc}: iters {iters}, inertia {inert0:.4e} -> {inert:.4e}")
+    assert inert < inert0
