@@ -63,10 +63,12 @@ def kernel_table(trace_csv: str, title: str, command: str, top: int = 30) -> str
     return "\n".join(out) + "\n"
 
 
-def concurrent_spans(trace_csv: str, kernel_regex: str):
+def concurrent_spans(trace_csv: str, kernel_regex: str, gap_ns: int = 0):
     """Dispatches matching ``kernel_regex`` grouped into runs of overlapping
-    intervals (the size classes of one call run concurrently); returns the
-    spans (first start to last end, ns) and the number of dispatches of each."""
+    intervals (the size classes of one call run concurrently; with gap_ns > 0,
+    also dispatches that start at most gap_ns after the run's end, such as the
+    back-to-back launches of one class); returns the spans (first start to
+    last end, ns) and the number of dispatches of each."""
     header, rows = _rows(trace_csv)
     iname = _col(header, "kernel_name")
     i0 = _col(header, "start_timestamp")
@@ -75,7 +77,7 @@ def concurrent_spans(trace_csv: str, kernel_regex: str):
     iv = sorted((int(r[i0]), int(r[i1])) for r in rows if pat.search(r[iname]))
     spans, counts = [], []
     for a, b in iv:
-        if spans and a <= spans[-1][1]:
+        if spans and a <= spans[-1][1] + gap_ns:
             spans[-1][1] = max(spans[-1][1], b)
             counts[-1] += 1
         else:
@@ -147,6 +149,8 @@ def main(argv=None) -> int:
     k.add_argument("--command", required=True)
     k.add_argument("--span", default="", help="regex of concurrently launched kernels whose common span to report")
     k.add_argument("--span-min-dispatches", type=int, default=2)
+    k.add_argument("--span-gap-us", type=float, default=0.0,
+                   help="also join dispatches starting at most this long after a run's end")
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -161,11 +165,12 @@ def main(argv=None) -> int:
     if a.cmd == "kernels":
         sys.stdout.write(kernel_table(a.trace_csv, a.title, a.command))
         if a.span:
-            spans, counts = concurrent_spans(a.trace_csv, a.span)
+            spans, counts = concurrent_spans(a.trace_csv, a.span, int(a.span_gap_us * 1e3))
             sel = [s for s, c in zip(spans, counts) if c >= a.span_min_dispatches]
             if sel:
+                gap = f", gaps up to {a.span_gap_us:g} us joined" if a.span_gap_us > 0 else ""
                 sys.stdout.write(f"\nConcurrent span of `{a.span}` ({len(sel)} calls with >= "
-                                 f"{a.span_min_dispatches} overlapping dispatches): mean "
+                                 f"{a.span_min_dispatches} overlapping dispatches{gap}): mean "
                                  f"{sum(sel) / len(sel) / 1e3:.1f} us, min {min(sel) / 1e3:.1f} us, "
                                  f"max {max(sel) / 1e3:.1f} us.\n")
         return 0
