@@ -1,4 +1,4 @@
-"""Block orderings on the GPU (Morton, maxmin) against the oracle bit for
+"""Block orderings on the GPU (Morton, Hilbert, KD-tree, maxmin) against the oracle bit for
 bit, and the ordering study of Section 3 in small: KL divergences (eq.
 (kl-gaussian-vecchia)) of random, Morton, Hilbert, KD-tree and maxmin
 orders, GPU against the oracle."""
