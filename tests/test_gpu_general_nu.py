@@ -214,3 +214,32 @@ def test_mle_estimates_nu():
     assert joint.loglik >= ll_true - 1e-6 * abs(ll_true)
     assert joint.loglik >= fixed.loglik - 1e-6 * abs(fixed.loglik)
     assert abs(joint.theta[3] - 1.5) < abs(0.8 - 1.5)
+
+
+def test_nu_derivative_3d_anisotropic():
+    """d l / d nu on a 3-D anisotropic problem (range a common scale,
+    multipliers (1, 1, 0.2)) against the oracle's trace formula."""
+    from paper_2410_04477_amd import api
+    th = W.Theta(1.0, 0.1, 1e-3, 1.8, (1.0, 1.0, 0.2))
+    pb = problem("gnu-dnu-3d", 500, 3, 40, 25, th.replace(nu=1.5), 99, zmax=0.2)
+    args = (pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"])
+    ref = OL.grad_nu_trace(*args, th)
+    plan = api.Plan(_t(pb["block_ptr"], torch.int32), _t(pb["nbr_ptr"], torch.int32), 500, 1)
+    got = float(api.loglik_dnu(plan, _t(pb["locs_perm"]), _t(pb["y_perm"]), _t(pb["nbr_idx"], torch.int32), [th])[0])
+    print(f"3-D: dl/dnu gpu {got:.9f} oracle {ref.sum():.9f}")
+    assert abs(got - ref.sum()) <= 1e-6 * np.abs(ref).sum()
+
+
+def test_mle_estimates_nu_fp32_bulk():
+    """The joint fit with the FP32-bulk gradient (then the FP64 polish) reaches
+    the FP64 joint fit's likelihood."""
+    from paper_2410_04477_amd import mle
+    from paper_2410_04477_amd.model import BlockVecchia
+    th = W.Theta(1.0, 0.08, 0.01, 1.5)
+    pb = problem("gnu-mle-nu", 2000, 2, 200, 30, th, 87)
+    mod = BlockVecchia.from_prepared(_t(pb["locs_perm"]), _t(pb["y_perm"]), _t(pb["block_ptr"], torch.int32),
+                                     _t(pb["nbr_ptr"], torch.int32), _t(pb["nbr_idx"], torch.int32), 0.8)
+    r64 = mle.fit(mod, (1.0, 0.05, 0.05, 0.8), "fp64", max_evals=120, estimate_nu=True)
+    r32 = mle.fit(mod, (1.0, 0.05, 0.05, 0.8), "fp32", max_evals=120, estimate_nu=True)
+    print("fp64", r64.theta, r64.loglik, "fp32-bulk + polish", r32.theta, r32.loglik)
+    assert r32.loglik >= r64.loglik - 1e-6 * abs(r64.loglik)
