@@ -227,6 +227,15 @@ def main() -> int:
             model.loglik_grad([th_g[i % len(th_g)]], "fp32")
         torch.cuda.synchronize()
         variants["fp32_loglik_grad_nu1.0_bessel_evals_per_s"] = k2 / (time.perf_counter() - t0)
+        # d l / d nu (two FP64 Bessel-form log-likelihoods per theta)
+        log("timing d l / d nu at nu = 1.0")
+        model.loglik_dnu(th_g[:1])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k2):
+            model.loglik_dnu([th_g[i % len(th_g)]])
+        torch.cuda.synchronize()
+        variants["fp64_loglik_dnu_nu1.0_evals_per_s"] = k2 / (time.perf_counter() - t0)
     tt = [thetas[0]]
     l64, g64, _, _, gp64 = model.loglik_grad(tt, "fp64", want_partial=True)
     l32, g32, c32, _, _ = model.loglik_grad(tt, "fp32")
