@@ -80,3 +80,68 @@ def test_ordering_kl_study():
             assert abs(kl_gpu - kl_or) <= 1e-6 * max(1.0, kl_or)
     for r in rows:
         print(f"bc={r[0]} {r[1]}: KL {r[2]:.3f}")
+
+
+def test_kl_trends_16k():
+    """The accuracy study of Section 3 near its size: n = 16,000 points in the
+    unit square (the paper's 20,000 exceed the 16,383 points one block of the
+    large-block path holds, and the exact term is one block of every point),
+    KL = l_exact(theta; 0) - l(theta; 0) (eq. (kl-gaussian-vecchia)).
+    (1) beta = 0.052537, nu = 1.5, 60 neighbours, random block order: KL
+    falls as the block count grows (500, 1,500, 5,000).  (2) Smoothness
+    nu = 0.5, 1.5, 2.5 at the Table 1 ranges: block Vecchia with 1,500 blocks
+    and 150 neighbours against classic Vecchia (one point per block, random
+    point order, 30 neighbours); classic Vecchia's KL grows with nu more than
+    block Vecchia's (the paper's robustness finding)."""
+    from paper_2410_04477_amd import api
+    n = 16000
+    s = W.rng(2024).random((n, 2))
+    zero = _t(np.zeros(n))
+    bp1, np1 = _t(np.array([0, n]), torch.int32), _t(np.array([0, 0]), torch.int32)
+    ex_plan = api.Plan(bp1, np1, n, 1)
+    sl = _t(s)
+
+    cache = {}
+
+    def exact(th):   # the large-block factorisation of all 16,000 points is the slow part
+        if th not in cache:
+            cache[th] = float(api.loglik(ex_plan, sl, zero, _t(np.zeros(1), torch.int32), [th])[0][0])
+        return cache[th]
+
+    def bv(th, bc, m, seed):
+        perm, bp, _ = api.blocks(sl, bc, torch.tensor(W.kmeans_init(n, bc, seed), device=DEV),
+                                 torch.tensor(W.block_permutation(bc, seed), device=DEV), [1.0, 1.0], 10)
+        lp = api.permute_rows(sl, perm)
+        npt, nid = api.neighbors(lp, bp, m, [1.0, 1.0])
+        plan = api.Plan(bp, npt, n, 1)
+        return float(api.loglik(plan, lp, zero, nid, [th])[0][0])
+
+    def cv(th, m, seed):
+        order = torch.tensor(W.point_permutation(n, seed), device=DEV)
+        lp = api.permute_rows(sl, order)
+        bp = _t(np.arange(n + 1), torch.int32)
+        npt, nid = api.neighbors(lp, bp, m, [1.0, 1.0])
+        return float(api.loglik(api.Plan(bp, npt, n, 1), lp, zero, nid, [th])[0][0])
+
+    th = W.Theta(1.0, 0.052537, 0.0, 1.5)
+    ex = exact(th)
+    kls = []
+    for bc in (500, 1500, 5000):
+        kls.append(ex - bv(th, bc, 60, 2100 + bc))
+        print(f"BV-{bc}-60-random (nu 1.5): KL {kls[-1]:.4f}")
+    assert all(k >= 0 for k in kls)
+    assert kls[0] > kls[1] > kls[2]
+
+    betas = {0.5: 0.078809, 1.5: 0.052537, 2.5: 0.042869}   # Table 1, effective range 0.3
+    rows = {}
+    for nu, beta in betas.items():
+        t = W.Theta(1.0, beta, 0.0, nu)
+        e = exact(t)
+        rows[nu] = (e - bv(t, 1500, 150, 2200), e - cv(t, 30, 2300))
+        print(f"nu {nu}, beta {beta}: KL BV-1500-150-random {rows[nu][0]:.3e}, CV-16K-30-random {rows[nu][1]:.3e}")
+    for b, c in rows.values():
+        assert b >= 0 and c >= 0
+    growth_bv = rows[2.5][0] / max(rows[0.5][0], 1e-12)
+    growth_cv = rows[2.5][1] / max(rows[0.5][1], 1e-12)
+    print(f"KL growth nu 0.5 -> 2.5: BV {growth_bv:.2f}x, CV {growth_cv:.2f}x")
+    assert growth_cv > growth_bv
