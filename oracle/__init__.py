@@ -11,10 +11,12 @@ Contents (each function cites the passage of the paper it follows):
                 d rho / d nu from the integral form of K_nu
   preprocess  - K-means (Section 2.1), random block order, block nearest
                 neighbours of each block centroid among earlier blocks
-  loglik      - Alg. 1 chain in numpy; exact GP, eq. (likeli); classic Vecchia;
+  loglik      - block terms of eq. (vecchia-vector) by their definition (joint
+                minus neighbour Gaussian log-density); exact GP, eq. (likeli);
+                classic Vecchia;
                 trace-formula gradient (also in nu); KL divergence, eq.
                 (kl-gaussian-vecchia)
-  coracle     - the same Alg. 1 chain and gradient in plain C with OpenMP over
+  coracle     - the same block terms and gradient in plain C with OpenMP over
                 blocks (csrc/bv_oracle.c), for the larger workloads
   simulate    - exact-GP and sequential-Vecchia data simulators
   ordering    - Morton, Hilbert, KD-tree and maxmin block orderings (Section 2.1)

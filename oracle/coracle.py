@@ -61,7 +61,7 @@ def _c(a, dt):
 
 
 def block_terms(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta, nthreads: int = 0):
-    """Per-block terms l_i (Alg. 1 chain) in FP64; NaN marks a non-PD block."""
+    """Per-block terms l_i = log N(y_J) - log N(y_N) in FP64; NaN marks a non-PD block."""
     locs = _c(locs_perm, np.float64)
     y = _c(y_perm, np.float64)
     bp = _c(block_ptr, np.int64)

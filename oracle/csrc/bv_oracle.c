@@ -3,18 +3,16 @@
  * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
  * load this library.  It shares no code with the HIP library.
  *
- * bvo_loglik   : per block, the chain of Alg. 1 in the paper's order --
- *                Sigma^lk, Sigma^con, Sigma^cross (Matern, eq. (maternkernel),
- *                plus the nugget on same-index pairs); L = POTRF(Sigma^con);
- *                Sigma'^cross = L^-1 Sigma^cross (TRSM); y' = L^-1 y_NN (TRSV);
- *                Sigma^cor = Sigma'^cross^T Sigma'^cross (GEMM);
- *                mu = Sigma'^cross^T y' (GEMV); Sigma^new = Sigma^lk - Sigma^cor;
- *                L' = POTRF(Sigma^new); v = L'^-1 (y_B - mu); u = v^T v;
- *                d = 2 sum log diag L'; l_i = -(u + d + l_i log 2 pi)/2.
+ * bvo_loglik   : per block, one factor of eq. (vecchia-vector) by its
+ *                definition, log p(y_B | y_N) = log N(y_J; 0, K_J) -
+ *                log N(y_N; 0, K_N) with J = N u B: each Gaussian log-density
+ *                from its own dense Cholesky factorisation (Matern covariance,
+ *                eq. (maternkernel), plus the nugget on same-index pairs).
  * bvo_grad     : per block, the gradient of log p(y_J) - log p(y_N) w.r.t.
  *                (sigma2, beta, nugget) by the textbook trace formula
  *                0.5 tr[(alpha alpha^T - K^-1) dK], alpha = K^-1 y, with K^-1 from an
  *                explicit triangular inverse.
+ * bvo_simulate : draws from the block Vecchia density (data generation).
  * Blocks run in parallel (OpenMP); each writes its own slot, and the caller
  * sums the slots in block order.
  */
@@ -93,51 +91,36 @@ static void trsm_lower(const double* L, int n, double* B, int c) {
   }
 }
 
+/* log N(y_S; 0, K_S) for the points S = idx[0..p): K_S = L L^T, w = L^-1 y_S,
+ * value -p log(2 pi) / 2 - sum log L_jj - w^T w / 2.  NaN if K_S is not PD.
+ * work: p * p + p doubles. */
+static double logpdf(const double* locs, const double* y, int d, const int64_t* idx, int p,
+                     const bvo_theta* th, double* work) {
+  double* K = work;
+  double* w = K + (size_t)p * p;
+  for (int i = 0; i < p; ++i) {
+    for (int j = 0; j < p; ++j) K[i * p + j] = cov(locs + idx[i] * d, locs + idx[j] * d, d, th, i == j);
+    w[i] = y[idx[i]];
+  }
+  if (potrf(K, p)) return NAN;
+  trsm_lower(K, p, w, 1);
+  double q = 0.0, ld = 0.0;
+  for (int i = 0; i < p; ++i) {
+    q += w[i] * w[i];
+    ld += log(K[i * p + i]);
+  }
+  return -0.5 * p * BVO_LOG2PI - ld - 0.5 * q;
+}
+
+/* One block term: log N(y_J) - log N(y_N), J = (neighbours, block points). */
 static double block_loglik(const double* locs, const double* y, int d, int64_t b0, int64_t b1,
-                           const int64_t* nn, int m, const bvo_theta* th, double* work) {
+                           const int64_t* nn, int m, const bvo_theta* th, int64_t* J, double* work) {
   int l = (int)(b1 - b0);
-  double* lk = work;                 /* l x l */
-  double* con = lk + l * l;          /* m x m */
-  double* cross = con + m * m;       /* m x l */
-  double* ynn = cross + m * l;       /* m */
-  double* mu = ynn + m;              /* l */
-  double* r = mu + l;                /* l */
-  for (int i = 0; i < l; ++i)
-    for (int j = 0; j < l; ++j)
-      lk[i * l + j] = cov(locs + (b0 + i) * d, locs + (b0 + j) * d, d, th, i == j);
-  for (int i = 0; i < m; ++i) {
-    for (int j = 0; j < m; ++j)
-      con[i * m + j] = cov(locs + nn[i] * d, locs + nn[j] * d, d, th, i == j);
-    for (int j = 0; j < l; ++j)
-      cross[i * l + j] = cov(locs + nn[i] * d, locs + (b0 + j) * d, d, th, 0);
-    ynn[i] = y[nn[i]];
-  }
-  for (int j = 0; j < l; ++j) mu[j] = 0.0;
-  if (m > 0) {
-    if (potrf(con, m)) return NAN;          /* L = POTRF(Sigma^con) */
-    trsm_lower(con, m, cross, l);           /* Sigma'^cross = L^-1 Sigma^cross */
-    trsm_lower(con, m, ynn, 1);             /* y' = L^-1 y_NN */
-    for (int i = 0; i < l; ++i)             /* Sigma^new = Sigma^lk - Sigma'^T Sigma' */
-      for (int j = 0; j < l; ++j) {
-        double s = 0.0;
-        for (int k = 0; k < m; ++k) s += cross[k * l + i] * cross[k * l + j];
-        lk[i * l + j] -= s;
-      }
-    for (int i = 0; i < l; ++i) {           /* mu = Sigma'^T y' */
-      double s = 0.0;
-      for (int k = 0; k < m; ++k) s += cross[k * l + i] * ynn[k];
-      mu[i] = s;
-    }
-  }
-  if (potrf(lk, l)) return NAN;             /* L' = POTRF(Sigma^new) */
-  for (int i = 0; i < l; ++i) r[i] = y[b0 + i] - mu[i];
-  trsm_lower(lk, l, r, 1);                  /* v = L'^-1 (y_B - mu) */
-  double u = 0.0, det = 0.0;
-  for (int i = 0; i < l; ++i) {
-    u += r[i] * r[i];
-    det += log(lk[i * l + i]);
-  }
-  return -0.5 * (u + 2.0 * det + l * BVO_LOG2PI);
+  for (int k = 0; k < m; ++k) J[k] = nn[k];
+  for (int k = 0; k < l; ++k) J[m + k] = b0 + k;
+  double v = logpdf(locs, y, d, J, m + l, th, work);
+  if (m > 0) v -= logpdf(locs, y, d, J, m, th, work);
+  return v;
 }
 
 /* Gradient of log N(y_S; 0, K_S) w.r.t. (sigma2, beta, nugget), S = idx[0..p). */
@@ -199,7 +182,8 @@ int64_t bvo_loglik_sel(const double* locs, const double* y, int64_t n, int32_t d
   bvo_theta th = {theta7[0], theta7[1], theta7[2], theta7[3], {theta7[4], theta7[5], theta7[6]}};
   int lmax, mmax;
   max_block(block_ptr, bc, nbr_ptr, &lmax, &mmax);
-  size_t wsz = (size_t)lmax * lmax + (size_t)mmax * mmax + (size_t)mmax * lmax + mmax + 2 * lmax + 8;
+  const int pmax = lmax + mmax;
+  size_t wsz = (size_t)pmax * pmax + pmax + 8;
   int64_t bad = 0;
 #ifdef _OPENMP
   if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -207,15 +191,17 @@ int64_t bvo_loglik_sel(const double* locs, const double* y, int64_t n, int32_t d
 #pragma omp parallel reduction(+ : bad)
   {
     double* work = (double*)malloc(sizeof(double) * wsz);
+    int64_t* J = (int64_t*)malloc(sizeof(int64_t) * (pmax + 1));
 #pragma omp for schedule(dynamic, 16)
     for (int64_t q = 0; q < nsel; ++q) {
       int64_t i = sel ? sel[q] : q;
       int m = (int)(nbr_ptr[i + 1] - nbr_ptr[i]);
-      double v = block_loglik(locs, y, d, block_ptr[i], block_ptr[i + 1], nbr_idx + nbr_ptr[i], m, &th, work);
+      double v = block_loglik(locs, y, d, block_ptr[i], block_ptr[i + 1], nbr_idx + nbr_ptr[i], m, &th, J, work);
       partial[q] = v;
       if (isnan(v)) bad += 1;
     }
     free(work);
+    free(J);
   }
   return bad;
 }

@@ -1,15 +1,18 @@
 """Block Vecchia log-likelihood and its reference quantities, numpy FP64.
 
-* block_loglik_alg1 follows Alg. 1 (correction items, then independent
-  computation) step by step for one block, in the paper's notation.
-* loglik sums the per-block terms in block order, as in the final loop of
-  Alg. 1: l <- l - (u_i + d_i + l_i log 2 pi) / 2.
-* exact_loglik is eq. (likeli) by a dense Cholesky.
+* block_term is the definition of one factor of eq. (vecchia-vector): the
+  conditional log-density log p(y_B | y_N), written as the joint Gaussian
+  log-density of y_J, J = N u B, minus that of y_N, each by its own dense
+  Cholesky factorisation.  Alg. 1 reaches the same value (up to rounding
+  order) through its Cholesky / triangular-solve / Schur chain; the oracle
+  does not follow that chain.
+* loglik sums the per-block terms in block order.
+* exact_loglik is eq. (likeli) through the library's log-determinant and
+  linear solve (no Cholesky code shared with block_term).
 * classic_vecchia_loglik is the univariate Vecchia product (Section 1), an
   independent point-wise loop used for the block-size-1 check.
 * grad_trace is the textbook Gaussian log-density gradient applied to each
-  block's joint and neighbour densities (the block term of eq.
-  (vecchia-vector) is log p(y_J) - log p(y_N)).
+  block's joint and neighbour densities.
 * grad_nu_trace is the same trace formula for the smoothness nu, with
   d C / d nu from the integral form of d K_nu / d nu (matern.drho_dnu).
 * kl_divergence is eq. (kl-gaussian-vecchia).
@@ -23,33 +26,26 @@ from . import matern
 from .matern import LOG_2PI
 
 
-def _chol_lower(a: np.ndarray) -> np.ndarray:
-    return np.linalg.cholesky(a)
+def _logpdf(s, y, theta) -> float:
+    """log N(y; 0, K(theta)) of the points s: one dense Cholesky K = L L^T,
+    w = L^-1 y, log N = -|s| log(2 pi) / 2 - sum log diag L - w^T w / 2."""
+    K = matern.cov(s, s, theta, same=True)
+    L = np.linalg.cholesky(K)
+    w = linalg.solve_triangular(L, y, lower=True)
+    return -0.5 * y.size * LOG_2PI - float(np.sum(np.log(np.diag(L)))) - 0.5 * float(w @ w)
 
 
-def block_loglik_alg1(s_b, y_b, s_nn, y_nn, theta) -> float:
-    """One block of Alg. 1.  s_b: l x d block locations, s_nn: m x d neighbour
-    locations (m may be 0)."""
-    l = s_b.shape[0]
-    sig_lk = matern.cov(s_b, s_b, theta, same=True)                # Sigma^lk
-    if s_nn.shape[0] > 0:
-        sig_con = matern.cov(s_nn, s_nn, theta, same=True)         # Sigma^con
-        sig_cross = matern.cov(s_nn, s_b, theta)                   # Sigma^cross (m x l)
-        L = _chol_lower(sig_con)                                   # batchedPOTRF
-        sig_cross_p = linalg.solve_triangular(L, sig_cross, lower=True)   # batchedTRSM
-        y_nn_p = linalg.solve_triangular(L, y_nn, lower=True)      # batchedTRSV
-        sig_cor = sig_cross_p.T @ sig_cross_p                      # batchedGEMM
-        mu_cor = sig_cross_p.T @ y_nn_p                            # batchedGEMV
-        sig_new = sig_lk - sig_cor                                 # elementwise
-        mu_new = mu_cor
-    else:
-        sig_new = sig_lk
-        mu_new = np.zeros(l)
-    Lp = _chol_lower(sig_new)                                      # batchedPOTRF
-    v = linalg.solve_triangular(Lp, y_b - mu_new, lower=True)      # batchedTRSV
-    u = float(v @ v)                                               # batchedDotProduct
-    d = 2.0 * float(np.sum(np.log(np.diag(Lp))))                   # 2 log det L'
-    return -0.5 * (u + d + l * LOG_2PI)
+def block_term(s_b, y_b, s_nn, y_nn, theta) -> float:
+    """One factor of eq. (vecchia-vector), log p(y_B | y_N) =
+    log N(y_J; 0, K_J) - log N(y_N; 0, K_N) with J = N u B.  s_b: l x d block
+    locations, s_nn: m x d neighbour locations (m may be 0: then the block's
+    marginal density)."""
+    sj = np.vstack([s_nn, s_b]) if s_nn.shape[0] else s_b
+    yj = np.concatenate([y_nn, y_b]) if s_nn.shape[0] else y_b
+    v = _logpdf(sj, yj, theta)
+    if s_nn.shape[0]:
+        v -= _logpdf(s_nn, y_nn, theta)
+    return v
 
 
 def block_terms(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta, blocks=None) -> np.ndarray:
@@ -60,12 +56,12 @@ def block_terms(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta, blocks=No
     for i in sel:
         a, b = int(block_ptr[i]), int(block_ptr[i + 1])
         nn = nbr_idx[nbr_ptr[i]:nbr_ptr[i + 1]]
-        out.append(block_loglik_alg1(locs_perm[a:b], y_perm[a:b], locs_perm[nn], y_perm[nn], theta))
+        out.append(block_term(locs_perm[a:b], y_perm[a:b], locs_perm[nn], y_perm[nn], theta))
     return np.array(out)
 
 
 def loglik(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta) -> float:
-    """Sum of block terms in block order (Alg. 1, final loop)."""
+    """Sum of the block terms in block order, eq. (vecchia-vector)."""
     t = block_terms(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta)
     acc = 0.0
     for v in t:
@@ -74,12 +70,14 @@ def loglik(locs_perm, y_perm, block_ptr, nbr_ptr, nbr_idx, theta) -> float:
 
 
 def exact_loglik(locs, y, theta) -> float:
-    """eq. (likeli) by dense Cholesky."""
+    """eq. (likeli): -n log(2 pi) / 2 - log det(K) / 2 - y^T K^-1 y / 2, with the
+    library's log-determinant (LU) and linear solve."""
     n = locs.shape[0]
     K = matern.cov(locs, locs, theta, same=True)
-    L = _chol_lower(K)
-    w = linalg.solve_triangular(L, y, lower=True)
-    return -0.5 * n * LOG_2PI - float(np.sum(np.log(np.diag(L)))) - 0.5 * float(w @ w)
+    sign, logdet = np.linalg.slogdet(K)
+    if sign <= 0:
+        return float("nan")
+    return -0.5 * n * LOG_2PI - 0.5 * logdet - 0.5 * float(y @ np.linalg.solve(K, y))
 
 
 def classic_vecchia_loglik(locs_ordered, y_ordered, nbrs, theta) -> float:

@@ -2,8 +2,9 @@
 results the mathematics fixes independently of the oracle's own code:
 the exact GP density (eq. (likeli)) when every block conditions on all
 earlier points (eq. (bv)), classic Vecchia at block size 1, permutation
-invariance inside blocks, the joint-density identity per block (library
-multivariate-normal log-pdf), KL properties (eq. (kl-gaussian-vecchia)),
+invariance inside blocks, the conditional form of each block term (library
+multivariate-normal log-pdf of y_B with the conditional mean and Schur
+complement from library solves), KL properties (eq. (kl-gaussian-vecchia)),
 and finite differences of the log-likelihood for the gradient."""
 import numpy as np
 import pytest
@@ -91,21 +92,33 @@ def test_permutation_within_blocks_invariant():
     assert OL.loglik(lp2, yp2, bp, nptr, nidx2, theta) == pytest.approx(base, rel=1e-12)
 
 
-def test_block_term_is_joint_minus_neighbour_logpdf():
+def _conditional_logpdf(lp, yp, nn, blk, theta):
+    """log N(y_B; mu, S), mu = K_BN K_NN^-1 y_N, S = K_BB - K_BN K_NN^-1 K_NB
+    (library solves and the library's multivariate-normal log-pdf)."""
+    Kbb = matern.cov(lp[blk], lp[blk], theta, same=True)
+    if len(nn) == 0:
+        return stats.multivariate_normal(np.zeros(len(blk)), Kbb).logpdf(yp[blk])
+    Knn = matern.cov(lp[nn], lp[nn], theta, same=True)
+    Kbn = matern.cov(lp[blk], lp[nn], theta)
+    C = np.linalg.solve(Knn, Kbn.T)
+    mu = C.T @ yp[nn]
+    S = Kbb - Kbn @ C
+    return stats.multivariate_normal(mu, 0.5 * (S + S.T)).logpdf(yp[blk])
+
+
+def test_block_term_is_conditional_logpdf():
     theta = THETAS[3]
     s, y, pre = _problem(400, 25, 30, theta)
     lp, yp = pre["locs_perm"], y[pre["perm"]]
     bp, nptr, nidx = pre["block_ptr"], pre["nbr_ptr"], pre["nbr_idx"]
     terms = coracle.block_terms(lp, yp, bp, nptr, nidx, theta)
+    terms_np = OL.block_terms(lp, yp, bp, nptr, nidx, theta)
     for i in (0, 1, 7, 24):
         nn = nidx[nptr[i]:nptr[i + 1]]
-        J = np.concatenate([nn, np.arange(bp[i], bp[i + 1])])
-        KJ = matern.cov(lp[J], lp[J], theta, same=True)
-        ref = stats.multivariate_normal(np.zeros(len(J)), KJ).logpdf(yp[J])
-        if len(nn):
-            KN = matern.cov(lp[nn], lp[nn], theta, same=True)
-            ref -= stats.multivariate_normal(np.zeros(len(nn)), KN).logpdf(yp[nn])
+        blk = np.arange(bp[i], bp[i + 1])
+        ref = _conditional_logpdf(lp, yp, nn, blk, theta)
         assert terms[i] == pytest.approx(ref, rel=1e-9, abs=1e-9)
+        assert terms_np[i] == pytest.approx(ref, rel=1e-9, abs=1e-9)
 
 
 def test_c_and_numpy_oracles_agree_c1_shape():
@@ -163,8 +176,8 @@ def test_gradient_matches_fd_and_numpy(theta):
 @pytest.mark.parametrize("nu", [0.3, 0.8, 1.0, 2.0, 3.3])
 def test_general_nu_numpy_oracle(nu):
     """Any nu > 0 through the Bessel form: all-previous conditioning equals
-    the exact GP density, the block term is the joint minus the neighbour
-    log-pdf (library multivariate normal), and the trace-formula gradient
+    the exact GP density, the block term equals the conditional log-pdf
+    (library solves and multivariate normal), and the trace-formula gradient
     matches central differences."""
     theta = W.Theta(1.1, 0.08, 2e-3, nu)
     s, y, pre = _problem(90, 9, -1, theta)
@@ -178,13 +191,8 @@ def test_general_nu_numpy_oracle(nu):
     bp, npt, nid = pre["block_ptr"], pre["nbr_ptr"], pre["nbr_idx"]
     for i in (0, 4, 8):
         nn = nid[npt[i]:npt[i + 1]]
-        sj = np.vstack([lp[nn], lp[bp[i]:bp[i + 1]]])
-        kj = matern.cov(sj, sj, theta, same=True)
-        yj = np.concatenate([yp[nn], yp[bp[i]:bp[i + 1]]])
-        ref = stats.multivariate_normal(np.zeros(yj.size), kj).logpdf(yj)
-        if nn.size:
-            ref -= stats.multivariate_normal(np.zeros(nn.size), kj[:nn.size, :nn.size]).logpdf(yp[nn])
-        assert terms[i] == pytest.approx(ref, rel=1e-10)
+        ref = _conditional_logpdf(lp, yp, nn, np.arange(bp[i], bp[i + 1]), theta)
+        assert terms[i] == pytest.approx(ref, rel=1e-9)
     g = OL.grad_trace(*args, theta).sum(0)
     for k, name in enumerate(("sigma2", "beta", "nugget")):
         v, h = getattr(theta, name), 1e-6 * max(getattr(theta, name), 1e-3)

@@ -28,6 +28,33 @@ def test_kmeans_fixed_point_and_partition():
         assert np.all(np.diff(blk) > 0)              # ascending original index
 
 
+def test_kmeans_empty_cluster_reseed_hand_example():
+    # duplicate initial centroids: every point ties between clusters 0 and 1
+    # and goes to the lower index, so cluster 1 is empty after the first
+    # assignment.  Update: c0 = mean(0, 1, 2, 10) = 3.25; cluster 1 is re-seeded
+    # with the point farthest from its (updated) centroid, x = 10.  Reassign:
+    # {0, 1, 2} -> 0, {10} -> 1; update c = (1, 10); no change -> stop.
+    x = np.array([[0.0], [1.0], [2.0], [10.0]])
+    lab, cen = P.kmeans(x, [1.0], np.array([0, 0]), max_iter=30)
+    assert lab.tolist() == [0, 0, 0, 1]
+    np.testing.assert_array_equal(cen[:, 0], [1.0, 10.0])
+
+
+def test_kmeans_two_empty_clusters_take_farthest_points_in_order():
+    # three copies of x = 0 as initial centroids: clusters 1 and 2 start empty.
+    # After the update c0 = 33/5 = 6.6, squared distances to it are
+    # (43.56, 31.36, 21.16, 11.56, 179.56): cluster 1 takes x = 20 (farthest),
+    # cluster 2 the next, x = 0.  Then {0, 1, 2} -> 2, {10} -> 0, {20} -> 1,
+    # c = (10, 20, 1), and the next assignment changes nothing.
+    x = np.array([[0.0], [1.0], [2.0], [10.0], [20.0]])
+    lab, cen = P.kmeans(x, [1.0], np.array([0, 0, 0]), max_iter=30)
+    assert lab.tolist() == [2, 2, 2, 0, 1]
+    np.testing.assert_array_equal(cen[:, 0], [10.0, 20.0, 1.0])
+    # no cluster is lost and the result is a Lloyd fixed point
+    d2 = (x - cen[:, 0][None, :]) ** 2
+    assert np.all(d2[np.arange(5), lab] == d2.min(1))
+
+
 def test_kmeans_inertia_nonincreasing():
     n, bc = 800, 40
     s = W.rng(2).random((n, 3)) * [1, 1, 0.2]

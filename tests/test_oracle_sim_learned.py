@@ -37,6 +37,24 @@ def test_variogram_hand_example():
     assert g[k2] == pytest.approx((1 - 0) ** 2 / 2)
 
 
+@pytest.mark.parametrize("nu,slot", [(0.5, 0), (1.5, 1), (2.5, 2)])
+def test_features_hand_example(nu, slot):
+    # the three points above: gamma_6 = 13/4, gamma_12 = 1/2; subset variance
+    # mean(y^2) - mean(y)^2 = 10/3 - 16/9 = 14/9; features = gamma * 9/14 in
+    # the nu slot, zero elsewhere (96 = 3 slots x 32 bins)
+    s = np.array([[0.0, 0.0], [0.1, 0.0], [0.2, 0.0]])
+    y = np.array([1.0, 3.0, 0.0])
+    x = LR.features(s, y, nu)
+    assert x.shape == (96,)
+    ref = np.zeros(96)
+    ref[slot * 32 + 6] = 3.25 * 9.0 / 14.0
+    ref[slot * 32 + 12] = 0.5 * 9.0 / 14.0
+    np.testing.assert_allclose(x, ref, rtol=1e-14, atol=0.0)
+    # shifting y leaves both the variogram and the variance unchanged;
+    # scaling y by c leaves the normalised features unchanged too
+    np.testing.assert_allclose(LR.features(s, 2.5 * y + 7.0, nu), ref, rtol=1e-13, atol=0.0)
+
+
 def test_mlp_backward_matches_fd():
     p = LR.init_params(0, sizes=(6, 5, 4, 3))
     g = W.rng(1)
