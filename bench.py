@@ -51,6 +51,22 @@ def step_flops(p, m, l):
     return p ** 3 / 3.0 + p ** 2 + 30.0 * p * (p + 1) / 2.0 + 3.0 * m * m * l + 2.0 * m * m
 
 
+def value_flops(p):
+    """Algorithmic flops of one block's value: joint factorisation and solves
+    (p^3/3 + p^2) and covariance generation (30 per lower-triangle entry)."""
+    return p ** 3 / 3.0 + p ** 2 + 30.0 * p * (p + 1) / 2.0
+
+
+def span_roofline(kt, nclasses, flops, peak, kernel):
+    """Roofline over the span of one call's concurrent size-class launches
+    (HIP events on the class streams), averaged over the timed calls."""
+    span_ms, span_n = kt[nclasses]
+    span_s = span_ms / span_n / 1e3
+    return {"bound": "mfma", "achieved": flops / span_s / 1e12, "peak": peak / 1e12, "unit": "TFLOP/s",
+            "frac": flops / span_s / peak, "kernel": kernel, "avg_launch_ms": span_s * 1e3,
+            "flops_per_launch": flops}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -206,12 +222,18 @@ def main() -> int:
 
     # ---- variants and accuracy ----------------------------------------------
     variants = {}
+    flops_value = float(np.sum(value_flops(psz.astype(np.float64))))
     if not args.no_variants:
         k2 = max(3, args.steps // 2)
         for prec, grad in (("fp64", True), ("fp64", False), ("fp32", False)):
             log(f"timing {prec} {'loglik+grad' if grad else 'loglik'}")
-            wv, _, _ = timed(prec, grad, k2, 1)
-            variants[f"{prec}_{'loglik_grad' if grad else 'loglik'}_evals_per_s"] = k2 / wv
+            wv, _, ktv = timed(prec, grad, k2, 1, with_timing=True)
+            key = f"{prec}_{'loglik_grad' if grad else 'loglik'}"
+            variants[f"{key}_evals_per_s"] = k2 / wv
+            tname = "double" if prec == "fp64" else "float"
+            variants[f"{key}_roofline"] = span_roofline(
+                ktv, len(classes), flops_launch if grad else flops_value, FP64_PEAK if prec == "fp64" else FP32_PEAK,
+                f"bv_wave_kernel<{tname},G,{1 if grad else 0}> over {len(classes)} concurrent size classes")
         variants["fp32_loglik_grad_evals_per_s"] = evals
         variants["speedup_fp32_over_fp64_loglik_grad"] = evals / variants["fp64_loglik_grad_evals_per_s"]
         variants["speedup_fp32_over_fp64_loglik"] = (variants["fp32_loglik_evals_per_s"]
@@ -268,7 +290,8 @@ def main() -> int:
     # ---- CPU baseline: the FP64 oracle on a bounded sample of the same blocks --
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(model, plan, bp, npt, th0, args.cpu_seconds)
+        cpu, sample, o_l, o_g = cpu_baseline(model, plan, bp, npt, th0, args.cpu_seconds)
+        accuracy["vs_oracle"] = accuracy_vs_oracle(model, th0, sample, o_l, o_g)
 
     out = {
         "metric": METRIC,
@@ -404,17 +427,45 @@ def cpu_baseline(model, plan, bp, npt, th0, target_s):
 
     def run(S):
         t0 = time.perf_counter()
-        coracle.selected_terms(locs, y, bp, npt, nidx, th0, order[:S], with_grad=True, nthreads=cores)
-        return time.perf_counter() - t0
+        vals = coracle.selected_terms(locs, y, bp, npt, nidx, th0, order[:S], with_grad=True, nthreads=cores)
+        return time.perf_counter() - t0, vals
 
     S = min(bc, 1024)     # a pilot large enough that thread start-up does not dominate
-    dt = run(S)
+    dt, _ = run(S)
     S2 = int(min(bc, max(S, S * target_s / max(dt, 1e-3))))
-    dt = run(S2)
+    dt, (o_l, o_g) = run(S2)
     per_eval = dt * bc / S2
-    return {"value": 1.0 / per_eval, "unit": "evals/s", "cores": cores, "kind": "oracle",
-            "sample": f"{S2} of {bc} blocks (seeded random), FP64 loglik + gradient, scaled by {bc}/{S2}",
-            "seconds": dt}
+    return ({"value": 1.0 / per_eval, "unit": "evals/s", "cores": cores, "kind": "oracle",
+             "sample": f"{S2} of {bc} blocks (seeded random), FP64 loglik + gradient, scaled by {bc}/{S2}",
+             "seconds": dt}, order[:S2], o_l, o_g)
+
+
+def accuracy_vs_oracle(model, th0, sample, o_l, o_g):
+    """Per-block terms and gradient rows of the GPU (FP64 and FP32-bulk) at
+    the generating theta against the oracle values of the CPU-baseline leg, on
+    the blocks that leg evaluated (all of them when its time budget allows).
+    The inputs are the benchmark's own (simulated y, library neighbour lists):
+    a diagnostic beside the parity tests, which use oracle-side inputs."""
+    import numpy as np
+
+    th = [model.theta(th0.sigma2, th0.beta, th0.nugget)]
+    out = {"blocks": int(len(sample)), "of": int(model.plan.bc)}
+    scale_l = float(np.abs(o_l).sum())
+    scale_g = np.abs(o_g).sum(0)
+    for prec in ("fp64", "fp32"):
+        _, _, cnt, part, gpart = model.loglik_grad(th, prec, want_partial=True)
+        pl = part[0].cpu().numpy()[sample]
+        pg = gpart[0].cpu().numpy()[sample]
+        dl = pl - o_l
+        dg = pg - o_g
+        out[prec] = {"max_abs_dl_i": float(np.abs(dl).max()),
+                     "max_rel_dl_i": float(np.max(np.abs(dl) / np.maximum(np.abs(o_l), 1.0))),
+                     "rel_err_sum_l": float(abs(dl.sum()) / abs(o_l.sum())),
+                     "sum_abs_dl_over_sum_abs_l": float(np.abs(dl).sum() / scale_l),
+                     "grad_rel_err_normwise_rows": float(np.linalg.norm(dg) / np.linalg.norm(o_g)),
+                     "grad_err_of_sum_per_component_vs_sum_abs": [float(v) for v in np.abs(dg.sum(0)) / scale_g],
+                     "blocks_refactored": int(cnt[0, 0])}
+    return out
 
 
 if __name__ == "__main__":

@@ -200,8 +200,13 @@ typedef enum { VECCHIA_ENGINE_MFMA = 0, VECCHIA_ENGINE_TILES = 1, VECCHIA_ENGINE
  * Auxiliary workspace: plan->aux_ws_bytes bytes (0 when not needed), attached
  * with vecchia_plan_attach_aux before the first evaluation, holds the large
  * blocks' matrices and, for engine MFMA, the adjoint's per-block factor tiles
- * (at most 4 GiB; the adjoint launches in chunks that fit it).  One plan's
- * calls must not overlap in time (they share both workspaces). */
+ * (at most 4 GiB; the adjoint launches in chunks that fit it).  A smaller
+ * buffer is accepted down to the size that holds every large-block slot and
+ * one work item's FP64 factor tiles of the largest one-wave class (else
+ * VECCHIA_ENOMEM): the size classes then run one after another, the adjoint
+ * in as many launches as the buffer needs, and plan->aux_ws_bytes is lowered
+ * to the attached size.  One plan's calls must not overlap in time (they
+ * share both workspaces). */
 #define VECCHIA_MAX_BUCKETS 24
 #define VECCHIA_MAX_JOINT 175  /* largest m_i + l_i (both engines) */
 typedef struct {
@@ -231,6 +236,13 @@ typedef struct {
   int32_t kind;    /* 0 likelihood plan, 1 prediction plan (VECCHIA_PLAN_PREDICT) */
 } vecchia_plan;
 
+/* Layout of vecchia_plan as compiled into the library, for bindings that
+ * mirror the struct (for instance through ctypes): out[0] = sizeof(vecchia_plan),
+ * out[1 + k] = offsetof of the k-th field in declaration order.  Writes at most
+ * cap entries (out may be NULL) and returns the number of entries.  Host only;
+ * a binding compares these with its own mirror at load and refuses to run on
+ * a mismatch. */
+int32_t vecchia_plan_layout(int64_t* out, int32_t cap);
 size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
 /* Tile configuration of a size class (plan->bucket_cfg[q]) of an engine: tile
  * size R and tile-grid order G (joint capacity R*G; the matrix-core engine has

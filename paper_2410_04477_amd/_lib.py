@@ -81,9 +81,31 @@ SIGNATURES = {
     "vecchia_reorder_blocks": (ctypes.c_int, [P, I64, I32, P, P, I64, I32, P, P, P, P, SZ, P]),
     "vecchia_condsim_workspace_size": (SZ, [I64]),
     "vecchia_condsim": (ctypes.c_int, [P, P, I64, P, I32, P, P, P, P, P, P, P, SZ, P]),
+    "vecchia_plan_layout": (I32, [P, I32]),
 }
 
 _lib = None
+
+
+def plan_layout_mismatch(L: ctypes.CDLL, cls=Plan):
+    """None if the ctypes mirror `cls` has the library's vecchia_plan layout
+    (size and every field offset, in order), else a description of the first
+    difference."""
+    k = L.vecchia_plan_layout(None, 0)
+    buf = (ctypes.c_int64 * k)()
+    L.vecchia_plan_layout(buf, k)
+    lib_layout = list(buf)
+    mine = [ctypes.sizeof(cls)] + [getattr(cls, f[0]).offset for f in cls._fields_]
+    if lib_layout == mine:
+        return None
+    names = ["sizeof"] + [f[0] for f in cls._fields_]
+    for i in range(max(len(mine), len(lib_layout))):
+        a = lib_layout[i] if i < len(lib_layout) else None
+        b = mine[i] if i < len(mine) else None
+        if a != b:
+            what = names[i] if i < len(names) else f"entry {i}"
+            return f"vecchia_plan {what}: library {a}, binding {b}"
+    return "vecchia_plan layout differs"
 
 
 def lib() -> ctypes.CDLL:
@@ -99,6 +121,9 @@ def lib() -> ctypes.CDLL:
                 continue
             f.restype = res
             f.argtypes = args
+        bad = plan_layout_mismatch(L)
+        if bad:
+            raise VecchiaError(f"binding and library disagree on the plan layout ({bad}): rebuild the library")
         _lib = L
     return _lib
 

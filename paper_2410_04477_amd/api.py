@@ -135,7 +135,9 @@ class Plan:
     """Launch schedule for one block / neighbour structure (vecchia_plan_init)."""
 
     def __init__(self, block_ptr: torch.Tensor, nbr_ptr: torch.Tensor, n: int, max_theta: int = 1,
-                 engine: str = "mfma", predict: bool = False):
+                 engine: str = "mfma", predict: bool = False, aux_bytes: int | None = None):
+        """aux_bytes: cap on the auxiliary workspace (default: what the plan
+        asks for); a smaller one runs the adjoint in more launches."""
         _dev_check(block_ptr, nbr_ptr)
         if block_ptr.dtype != torch.int32 or nbr_ptr.dtype != torch.int32:
             raise ValueError("block_ptr / nbr_ptr must be int32")
@@ -151,7 +153,8 @@ class Plan:
         self.engine = engine
         self.aux_ws = None
         if self.c.aux_ws_bytes > 0:
-            self.aux_ws = torch.empty(int(self.c.aux_ws_bytes), dtype=torch.uint8, device=block_ptr.device)
+            nbytes = int(self.c.aux_ws_bytes) if aux_bytes is None else min(int(aux_bytes), int(self.c.aux_ws_bytes))
+            self.aux_ws = torch.empty(nbytes, dtype=torch.uint8, device=block_ptr.device)
             L.check(lib.vecchia_plan_attach_aux(ctypes.byref(self.c), _p(self.aux_ws), self.aux_ws.numel()),
                     "vecchia_plan_attach_aux")
         self.block_ptr, self.nbr_ptr = block_ptr, nbr_ptr
@@ -187,6 +190,14 @@ class Plan:
         cnt = (ctypes.c_int64 * (nb + 1))()
         L.check(L.lib().vecchia_plan_timing(ctypes.byref(self.c), ms, cnt, 1 if reset else 0), "vecchia_plan_timing")
         return [(float(ms[q]), int(cnt[q])) for q in range(nb + 1)]
+
+    def flags(self) -> torch.Tensor:
+        """Per (theta, block) flags of the last evaluation (device int32 view
+        [max_theta, bc] into the plan workspace): 1 FP32 guard tripped, 2 not
+        positive definite, 4 re-factorised in FP64."""
+        off = int(self.c.off_flag)
+        nt = int(self.c.max_theta)
+        return self.ws[off: off + 4 * nt * self.bc].view(torch.int32).view(nt, self.bc)
 
     def schedule(self) -> torch.Tensor:
         """Block ids grouped by size class (device int32 view into the plan workspace)."""

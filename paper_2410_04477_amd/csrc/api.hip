@@ -1,6 +1,7 @@
 // C ABI of the block Vecchia library: argument checking, workspace layout,
 // launch orchestration.  Every numerical step runs in the HIP kernels.
 #include <math.h>
+#include <stddef.h>
 #include <string.h>
 
 #include <vector>
@@ -18,6 +19,23 @@ using namespace bv;
 static inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 extern "C" int vecchia_version(void) { return 10000; }
+
+extern "C" int32_t vecchia_plan_layout(int64_t* out, int32_t cap) {
+#define BV_OFF(f) (int64_t) offsetof(vecchia_plan, f)
+  const int64_t v[] = {(int64_t)sizeof(vecchia_plan), BV_OFF(n), BV_OFF(bc), BV_OFF(max_theta), BV_OFF(nbuckets),
+                       BV_OFF(pmax), BV_OFF(lmax), BV_OFF(mmax), BV_OFF(bucket_cfg), BV_OFF(bucket_off),
+                       BV_OFF(lsum), BV_OFF(flops_la), BV_OFF(cov_entries), BV_OFF(ws), BV_OFF(ws_bytes),
+                       BV_OFF(off_sched), BV_OFF(off_partial), BV_OFF(off_flag), BV_OFF(off_list),
+                       BV_OFF(off_count), BV_OFF(off_chunk), BV_OFF(off_grad), BV_OFF(timing), BV_OFF(engine),
+                       BV_OFF(nlarge), BV_OFF(large_slots), BV_OFF(large_slot_elems), BV_OFF(aux_ws_bytes),
+                       BV_OFF(aux_ws), BV_OFF(bucket_lmax), BV_OFF(lds_bytes), BV_OFF(bucket_main), BV_OFF(exec),
+                       BV_OFF(kind)};
+#undef BV_OFF
+  const int32_t k = (int32_t)(sizeof(v) / sizeof(v[0]));
+  if (out)
+    for (int32_t i = 0; i < k && i < cap; ++i) out[i] = v[i];
+  return k;
+}
 
 extern "C" const char* vecchia_status_string(int status) {
   switch (status) {
@@ -487,12 +505,28 @@ extern "C" int vecchia_plan_timing(vecchia_plan* plan, double* ms, int64_t* laun
   return VECCHIA_OK;
 }
 
+// Smallest auxiliary workspace a plan can run with: every large-block slot,
+// and one work item's FP64 factor tiles of the largest one-wave class (the
+// adjoint then runs one item per launch).
+static size_t aux_min_bytes(const vecchia_plan* plan) {
+  size_t need = plan->nlarge > 0 ? (size_t)plan->large_slots * (size_t)plan->large_slot_elems * sizeof(double) : 0;
+  if (plan->engine == kEngineMfma && plan->kind == 0)
+    for (int q = 0; q < plan->nbuckets; ++q) {
+      const int g = plan->bucket_cfg[q] + 1;
+      if (plan->bucket_cfg[q] != kLargeCfg && wave_fits(g, false) && wave_tile_bytes(g, false) > need)
+        need = wave_tile_bytes(g, false);
+    }
+  return need;
+}
+
 extern "C" int vecchia_plan_attach_aux(vecchia_plan* plan, void* aux_workspace, size_t bytes) {
   if (!plan) return VECCHIA_EINVAL;
   if (plan->aux_ws_bytes == 0) return VECCHIA_OK;
   if (!aux_workspace) return VECCHIA_EINVAL;
-  if (bytes < plan->aux_ws_bytes) return VECCHIA_ENOMEM;
+  if (bytes < aux_min_bytes(plan)) return VECCHIA_ENOMEM;
   plan->aux_ws = aux_workspace;
+  // a smaller buffer than the plan asked for runs the adjoint in more launches
+  if (bytes < plan->aux_ws_bytes) plan->aux_ws_bytes = bytes;
   return VECCHIA_OK;
 }
 

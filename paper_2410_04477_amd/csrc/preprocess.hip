@@ -14,9 +14,11 @@
 // points lie within the cube's guaranteed radius, collects every earlier point
 // inside that radius, sorts by (squared distance, index) in LDS and keeps the
 // first m.  Blocks with few earlier points are searched exhaustively.
-#include <hipcub/hipcub.hpp>
 #include <math.h>
 #include <string.h>
+
+#include <rocprim/device/device_radix_sort.hpp>
+#include <rocprim/device/device_scan.hpp>
 
 #include <algorithm>
 #include <vector>
@@ -102,6 +104,7 @@ __global__ void km_init_kernel(KmArgs a, const int64_t* __restrict__ init_idx) {
 // nearest centroid of each point; centroids staged through LDS in chunks
 constexpr int KM_CHUNK = 512;
 __global__ void __launch_bounds__(256) km_assign_kernel(KmArgs a, int first) {
+#pragma clang fp contract(off)
   __shared__ double sc[KM_CHUNK * 3];
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   double x[3] = {0, 0, 0};
@@ -259,6 +262,19 @@ __global__ void km_update_kernel(KmArgs a, int* __restrict__ nempty) {
     a.cent[c * 3 + k] = a.lo[k] + ((double)a.fsum[c * 3 + k] / a.fscale) / (double)m;
 }
 
+// squared distance of each point to its (updated) centroid, for re-seeding
+// empty clusters; the same unfused arithmetic as the assignment
+__global__ void km_dist_kernel(KmArgs a) {
+#pragma clang fp contract(off)
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const int c = a.label[i];
+  double x[3] = {0, 0, 0};
+  for (int k = 0; k < a.d; ++k) x[k] = a.locs[i * a.d + k] * a.w[k];
+  const double t0 = x[0] - a.cent[c * 3], t1 = x[1] - a.cent[c * 3 + 1], t2 = x[2] - a.cent[c * 3 + 2];
+  a.dist[i] = t0 * t0 + t1 * t1 + t2 * t2;
+}
+
 // farthest point from its centroid (ties: lowest index), two-level
 __global__ void __launch_bounds__(256) argmax_kernel(const double* __restrict__ v, int64_t n,
                                                      double* __restrict__ pv, int64_t* __restrict__ pi) {
@@ -316,12 +332,16 @@ __global__ void pos_of_label_kernel(const int64_t* __restrict__ block_perm, int 
     atomicOr(bad, 1);
     return;
   }
-  pos_of_label[c] = i;
+  // pos_of_label starts at -1: a second claim of the same cluster is a duplicate
+  if (atomicCAS(&pos_of_label[c], -1, i) != -1) atomicOr(bad, 1);
 }
 
-__global__ void count_keys_kernel(const int* __restrict__ key, int64_t n, int* __restrict__ cnt) {
+__global__ void count_keys_kernel(const int* __restrict__ key, int64_t n, int nkeys, int* __restrict__ cnt) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) atomicAdd(&cnt[key[i]], 1);
+  if (i < n) {
+    const int k = key[i];
+    if (k >= 0 && k < nkeys) atomicAdd(&cnt[k], 1);
+  }
 }
 
 // ------------------------------------------------------------- neighbours --
@@ -587,15 +607,28 @@ static inline size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 namespace {
 template <typename P> P* at(void* base, size_t off) { return reinterpret_cast<P*>(static_cast<char*>(base) + off); }
 
+// rocPRIM device primitives: stable LSD radix sort of (key, value) pairs on
+// bits [b0, b1), and an exclusive prefix sum of int32.  A null `tmp` asks for
+// the temporary storage size in `bytes`.
+template <typename K, typename V>
+hipError_t radix_sort(void* tmp, size_t& bytes, const K* kin, K* kout, const V* vin, V* vout, int n, int b0, int b1,
+                      hipStream_t s) {
+  return rocprim::radix_sort_pairs(tmp, bytes, kin, kout, vin, vout, (unsigned int)n, (unsigned int)b0,
+                                   (unsigned int)b1, s);
+}
+hipError_t exclusive_sum(void* tmp, size_t& bytes, const int* in, int* out, int n, hipStream_t s) {
+  return rocprim::exclusive_scan(tmp, bytes, in, out, 0, (size_t)n, rocprim::plus<int>(), s);
+}
+
 size_t sort_temp_bytes_i32_i64(int64_t n, int nbits = 32) {
   size_t sz = 0;
-  hipcub::DeviceRadixSort::SortPairs((void*)nullptr, sz, (const int*)nullptr, (int*)nullptr, (const int64_t*)nullptr,
+  (void)radix_sort((void*)nullptr, sz, (const int*)nullptr, (int*)nullptr, (const int64_t*)nullptr,
                                      (int64_t*)nullptr, (int)n, 0, nbits, (hipStream_t)0);
   return sz;
 }
 size_t sort_temp_bytes_i32_i32(int64_t n, int nbits = 32) {
   size_t sz = 0;
-  hipcub::DeviceRadixSort::SortPairs((void*)nullptr, sz, (const int*)nullptr, (int*)nullptr, (const int*)nullptr,
+  (void)radix_sort((void*)nullptr, sz, (const int*)nullptr, (int*)nullptr, (const int*)nullptr,
                                      (int*)nullptr, (int)n, 0, nbits, (hipStream_t)0);
   return sz;
 }
@@ -631,7 +664,7 @@ BlocksLayout blocks_layout(int64_t n, int64_t bc) {
     L.gcur = o;   o = al256(o + sizeof(int) * (L.gcells + 1));
     L.gidx = o;   o = al256(o + sizeof(int) * bc);
     size_t sc = 0;
-    hipcub::DeviceScan::ExclusiveSum((void*)nullptr, sc, (const int*)nullptr, (int*)nullptr, (int)(L.gcells + 1),
+    (void)exclusive_sum((void*)nullptr, sc, (const int*)nullptr, (int*)nullptr, (int)(L.gcells + 1),
                                      (hipStream_t)0);
     L.gscan = o;  o = al256(o + sc);
   }
@@ -691,7 +724,7 @@ int km_assign(const KmArgs& a, const BlocksLayout& L, void* ws, const KmGrid* g,
   hipLaunchKernelGGL(km_grid_count_kernel, dim3(gb), dim3(256), 0, s, a, *g);
   PCHECK(hipGetLastError());
   size_t tmp = L.total - L.gscan;
-  PCHECK(hipcub::DeviceScan::ExclusiveSum(at<void>(ws, L.gscan), tmp, g->ccur, g->cstart, g->ncell + 1, s));
+  PCHECK(exclusive_sum(at<void>(ws, L.gscan), tmp, g->ccur, g->cstart, g->ncell + 1, s));
   hipLaunchKernelGGL(km_grid_cursor_kernel, dim3(cdiv64(g->ncell + 1, 256)), dim3(256), 0, s, *g);
   hipLaunchKernelGGL(km_grid_place_kernel, dim3(gb), dim3(256), 0, s, a, *g);
   hipLaunchKernelGGL(km_assign_grid_kernel, dim3(gn), dim3(256), 0, s, a, *g, first);
@@ -796,7 +829,10 @@ extern "C" int vecchia_blocks(const double* locs, int64_t n, int32_t d, const do
     PCHECK(hipStreamSynchronize(s));
     const int nempty = hflags[1];
     if (nempty > 0) {
-      // re-seed each empty cluster with the point farthest from its centroid
+      // re-seed each empty cluster, in cluster order, with the point farthest
+      // from its updated centroid (each point at most once)
+      hipLaunchKernelGGL(km_dist_kernel, dim3(gn), dim3(256), 0, s, a);
+      PCHECK(hipGetLastError());
       std::vector<int> hc(bc);
       PCHECK(hipMemcpyAsync(hc.data(), a.cnt, sizeof(int) * bc, hipMemcpyDeviceToHost, s));
       PCHECK(hipStreamSynchronize(s));
@@ -838,7 +874,17 @@ extern "C" int vecchia_blocks(const double* locs, int64_t n, int32_t d, const do
   int* pol = at<int>(workspace, L.pol);
   int* bad = a.changed + 2;
   hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, s, bad, 1, 0);
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(gb), dim3(256), 0, s, pol, (int)bc, -1);
   hipLaunchKernelGGL(pos_of_label_kernel, dim3(gb), dim3(256), 0, s, block_perm, (int)bc, pol, bad);
+  PCHECK(hipGetLastError());
+  {
+    // a block_perm that is not a permutation of 0..bc-1 stops here, before any
+    // kernel uses the positions as indices
+    int hbad = 0;
+    PCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    PCHECK(hipStreamSynchronize(s));
+    if (hbad) return VECCHIA_EINVAL;
+  }
   int* key = at<int>(workspace, L.key);
   int64_t* val = at<int64_t>(workspace, L.val);
   hipLaunchKernelGGL(pos_key_kernel, dim3(gn), dim3(256), 0, s, a.label, n, pol, key, val);
@@ -847,18 +893,15 @@ extern "C" int vecchia_blocks(const double* locs, int64_t n, int32_t d, const do
   while (((int64_t)1 << nbits) < bc) ++nbits;
   size_t tmp = sort_temp_bytes_i32_i64(n, nbits);
   if (L.sort + tmp > ws_bytes) return VECCHIA_ENOMEM;
-  PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key, at<int>(workspace, L.key2), val,
+  PCHECK(radix_sort(at<void>(workspace, L.sort), tmp, key, at<int>(workspace, L.key2), val,
                                             perm, (int)n, 0, nbits, s));
   int* kcnt = at<int>(workspace, L.kcnt);
   hipLaunchKernelGGL(fill_i32_kernel, dim3(cdiv64(bc + 1, 256)), dim3(256), 0, s, kcnt, (int)bc + 1, 0);
-  hipLaunchKernelGGL(count_keys_kernel, dim3(gn), dim3(256), 0, s, key, n, kcnt);
+  hipLaunchKernelGGL(count_keys_kernel, dim3(gn), dim3(256), 0, s, key, n, (int)bc, kcnt);
   PCHECK(hipGetLastError());
   std::vector<int> hk(bc);
-  int hbad = 0;
   PCHECK(hipMemcpyAsync(hk.data(), kcnt, sizeof(int) * bc, hipMemcpyDeviceToHost, s));
-  PCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
   PCHECK(hipStreamSynchronize(s));
-  if (hbad) return VECCHIA_EINVAL;
   std::vector<int> hp;
   hp.reserve(bc + 1);
   hp.push_back(0);
@@ -975,7 +1018,7 @@ static int neighbors_impl(const double* locs, int64_t n, int32_t d, const double
   while (((int64_t)1 << nbits) < (int64_t)g.ncell + 1) ++nbits;
   size_t tmp = sort_temp_bytes_i32_i32(n, nbits);
   if (L.sort + tmp > ws_bytes) return VECCHIA_ENOMEM;
-  PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key, key2, val, cell_pts, (int)n, 0,
+  PCHECK(radix_sort(at<void>(workspace, L.sort), tmp, key, key2, val, cell_pts, (int)n, 0,
                                             nbits, s));
   hipLaunchKernelGGL(cell_start_kernel, dim3(cdiv64(n + 1, 256)), dim3(256), 0, s, key2, n, g.ncell, cstart);
   int* status = at<int>(workspace, L.status);
@@ -1418,10 +1461,10 @@ OrderLayout order_layout(int64_t bc, int d) {
   L.pidx = o;  o = al256(o + sizeof(int) * (size_t)(bc / kMaxminStepThreads + 1) + 64);
   L.part = o;  o = al256(o + sizeof(double) * 6 * 1024);
   size_t st = 0, sc = 0;
-  hipcub::DeviceRadixSort::SortPairs((void*)nullptr, st, (const unsigned long long*)nullptr,
+  (void)radix_sort((void*)nullptr, st, (const unsigned long long*)nullptr,
                                      (unsigned long long*)nullptr, (const int64_t*)nullptr, (int64_t*)nullptr,
                                      (int)bc, 0, 64, (hipStream_t)0);
-  hipcub::DeviceScan::ExclusiveSum((void*)nullptr, sc, (const int*)nullptr, (int*)nullptr, (int)(bc + 1),
+  (void)exclusive_sum((void*)nullptr, sc, (const int*)nullptr, (int*)nullptr, (int)(bc + 1),
                                    (hipStream_t)0);
   L.sort = o;  o = al256(o + st);
   L.scan = o;  o = al256(o + sc);
@@ -1469,7 +1512,7 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
     PCHECK(hipGetLastError());
     size_t tmp = L.scan - L.sort;
     // radix sort is stable: equal keys keep the ascending block index
-    PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key,
+    PCHECK(radix_sort(at<void>(workspace, L.sort), tmp, key,
                                               at<unsigned long long>(workspace, L.key2), idx, order, ib, 0, 64, s));
   } else if (method == VECCHIA_ORDER_KDTREE) {
     unsigned long long* key = at<unsigned long long>(workspace, L.key);
@@ -1486,11 +1529,11 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
       size_t tmp = L.scan - L.sort;
       hipLaunchKernelGGL(kd_coord_kernel, dim3(g), dim3(256), 0, s, cen, ib, d, level % d, key, idx);
       PCHECK(hipGetLastError());
-      PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key, key2, idx, idx2, ib, 0, 64, s));
+      PCHECK(radix_sort(at<void>(workspace, L.sort), tmp, key, key2, idx, idx2, ib, 0, 64, s));
       hipLaunchKernelGGL(kd_node_kernel, dim3(g), dim3(256), 0, s, idx2, pos, ib, level, key, idx);
       PCHECK(hipGetLastError());
       tmp = L.scan - L.sort;
-      PCHECK(hipcub::DeviceRadixSort::SortPairs(at<void>(workspace, L.sort), tmp, key, key2, idx, order, ib, 0, 64, s));
+      PCHECK(radix_sort(at<void>(workspace, L.sort), tmp, key, key2, idx, order, ib, 0, 64, s));
       hipLaunchKernelGGL(kd_pos_kernel, dim3(g), dim3(256), 0, s, order, ib, pos);
       PCHECK(hipGetLastError());
     }
@@ -1519,7 +1562,7 @@ extern "C" int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_
   hipLaunchKernelGGL(block_sizes_kernel, dim3(cdiv64(bc + 1, 256)), dim3(256), 0, s, block_ptr, order, ib, sizes);
   PCHECK(hipGetLastError());
   size_t stmp = L.total - L.scan;
-  PCHECK(hipcub::DeviceScan::ExclusiveSum(at<void>(workspace, L.scan), stmp, sizes, block_ptr_out, ib + 1, s));
+  PCHECK(exclusive_sum(at<void>(workspace, L.scan), stmp, sizes, block_ptr_out, ib + 1, s));
   hipLaunchKernelGGL(gather_blocks_kernel, dim3(ib), dim3(64), 0, s, block_ptr, order, block_ptr_out, point_perm);
   PCHECK(hipGetLastError());
   return VECCHIA_OK;

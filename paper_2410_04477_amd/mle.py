@@ -9,9 +9,10 @@ import time
 
 import torch
 
+from ._lib import VecchiaError
 from .model import BlockVecchia, vecchia_loglik, vecchia_loglik_nu
 
-NUGGET_FLOOR = 1e-8  # log-parametrisation floor: eta_3 = log(nugget + floor)
+NUGGET_FLOOR = 1e-8  # a zero starting nugget starts at eta_3 = log(NUGGET_FLOOR)
 NU_LO, NU_HI = 0.06, 9.5   # nu = NU_LO + (NU_HI - NU_LO) sigmoid(eta_4), inside the Bessel form's [0.05, 10]
 
 
@@ -30,9 +31,28 @@ def _nu_to_eta(nu: float) -> float:
     return math.log(u / (1.0 - u))
 
 
+def to_natural(eta: torch.Tensor, estimate_nu: bool = False) -> torch.Tensor:
+    """(sigma2, range, nugget[, nu]) from the unconstrained eta: exp for the
+    first three, so every eta maps inside the domain (sigma2, range, nugget > 0)
+    however far the line search moves; nu = NU_LO + (NU_HI - NU_LO) sigmoid(eta_4)."""
+    e = torch.exp(eta[:3])
+    if estimate_nu:
+        return torch.cat([e, (NU_LO + (NU_HI - NU_LO) * torch.sigmoid(eta[3])).reshape(1)])
+    return e
+
+
+def to_eta(theta, estimate_nu: bool = False) -> list:
+    """Inverse of to_natural; a zero nugget starts at log(NUGGET_FLOOR)."""
+    s2, rg, nug = (float(v) for v in theta[:3])
+    e = [math.log(s2), math.log(rg), math.log(max(nug, NUGGET_FLOOR))]
+    if estimate_nu:
+        e.append(_nu_to_eta(float(theta[3])))
+    return e
+
+
 def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 200, tol_rel: float = 1e-10,
         history: int = 10, polish_evals: int = 30, estimate_nu: bool = False) -> MLEResult:
-    """L-BFGS (strong Wolfe line search) on eta = log(sigma2, range, nugget + floor),
+    """L-BFGS (strong Wolfe line search) on eta = log(sigma2, range, nugget),
     minimising -l / n.  Stops on relative change < tol_rel, small gradient, or
     max_evals evaluations.  With an FP32-bulk precision, a short FP64 L-BFGS
     pass (at most polish_evals evaluations) starts from the FP32 optimum: the
@@ -46,14 +66,12 @@ def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 2
         second = fit(model, first.theta, "fp64", polish_evals, tol_rel, history, 0, estimate_nu)
         return MLEResult(second.theta, second.loglik, first.evals + second.evals, first.iters + second.iters,
                          first.seconds + second.seconds, second.converged)
-    s2, rg, nug = (float(v) for v in theta0[:3])
-    e0 = [math.log(s2), math.log(rg), math.log(nug + NUGGET_FLOOR)]
     if estimate_nu:
         nu0 = float(theta0[3]) if len(theta0) > 3 else model.nu
         if not NU_LO < nu0 < NU_HI:
             raise ValueError(f"starting nu {nu0} outside ({NU_LO}, {NU_HI})")
-        e0.append(_nu_to_eta(nu0))
-    eta = torch.tensor(e0, dtype=torch.float64, requires_grad=True)
+        theta0 = tuple(theta0[:3]) + (nu0,)
+    eta = torch.tensor(to_eta(theta0, estimate_nu), dtype=torch.float64, requires_grad=True)
     opt = torch.optim.LBFGS([eta], lr=1.0, max_iter=max_evals, max_eval=max_evals, history_size=history,
                             tolerance_grad=1e-9, tolerance_change=tol_rel, line_search_fn="strong_wolfe")
     n = model.n
@@ -61,15 +79,12 @@ def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 2
 
     def closure():
         opt.zero_grad()
-        e = torch.exp(eta[:3])
-        if estimate_nu:
-            nu = NU_LO + (NU_HI - NU_LO) * torch.sigmoid(eta[3])
-            params = torch.stack([e[0], e[1], e[2] - NUGGET_FLOOR, nu])
-            ll = vecchia_loglik_nu(params, model, precision)
-        else:
-            params = torch.stack([e[0], e[1], e[2] - NUGGET_FLOOR])
-            ll = vecchia_loglik(params, model, precision)
-        if not torch.isfinite(ll):
+        params = to_natural(eta, estimate_nu)
+        try:
+            ll = vecchia_loglik_nu(params, model, precision) if estimate_nu else vecchia_loglik(params, model, precision)
+        except VecchiaError:
+            ll = None   # a theta the library rejects counts as a failed evaluation
+        if ll is None or not torch.isfinite(ll):
             ll = 0.0 * params.sum() - 1e300   # pushes the line search back (keeps the graph for backward)
         loss = -ll / n
         loss.backward()
@@ -80,11 +95,7 @@ def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 2
     t0 = time.perf_counter()
     opt.step(closure)
     dt = time.perf_counter() - t0
-    ed = eta.detach()
-    e = torch.exp(ed[:3])
-    th = (float(e[0]), float(e[1]), float(e[2] - NUGGET_FLOOR))
-    if estimate_nu:
-        th = th + (float(NU_LO + (NU_HI - NU_LO) * torch.sigmoid(ed[3])),)
+    th = tuple(float(v) for v in to_natural(eta.detach(), estimate_nu))
     ll = float(model.loglik([model.theta(*th)], precision)[0][0])
     st = opt.state[opt._params[0]]
     return MLEResult(th, ll, state["evals"], int(st.get("n_iter", 0)), dt, state["evals"] < max_evals)

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -70,3 +71,48 @@ def test_fp32_wave_kernels_keep_their_tiles_in_registers():
         if g <= 9:
             assert r["occupancy"] >= 2, (name, r)
     assert seen == 24   # value G = 1..11, fused gradient G = 1..9, split gradient G = 10, 11 (two kernels)
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
+def test_plan_layout_matches_binding_and_mismatch_is_caught():
+    """The ctypes mirror of vecchia_plan must have the library's layout; a
+    mirror with a field missing or a field of the wrong width is reported."""
+    import ctypes
+    from paper_2410_04477_amd import _lib as L
+    lib = L.lib()   # raises on a mismatch
+    assert L.plan_layout_mismatch(lib) is None
+    fields = list(L.Plan._fields_)
+
+    class Dropped(ctypes.Structure):
+        _fields_ = [f for f in fields if f[0] != "lsum"]
+
+    class Narrow(ctypes.Structure):
+        _fields_ = [(nm, ctypes.c_int32 if nm == "nlarge" else t) for nm, t in fields]
+
+    for bad in (Dropped, Narrow):
+        msg = L.plan_layout_mismatch(lib, bad)
+        assert msg is not None and msg.startswith("vecchia_plan "), msg
+
+
+def test_mle_parameter_map_stays_in_domain():
+    """L-BFGS works on eta = log(sigma2, range, nugget); every eta, however far
+    the line search moves it, maps to positive parameters, the map's gradient
+    is the chain rule of exp, and a zero starting nugget starts at the floor."""
+    import torch
+    from paper_2410_04477_amd import mle
+    eta = torch.tensor([0.3, -3.0, -80.0], dtype=torch.float64, requires_grad=True)
+    th = mle.to_natural(eta)
+    assert torch.all(th > 0)
+    assert float(th[2]) == pytest.approx(float(torch.exp(torch.tensor(-80.0, dtype=torch.float64))), rel=1e-15)
+    (th * torch.tensor([1.0, 2.0, 3.0], dtype=torch.float64)).sum().backward()
+    np_grad = eta.grad.numpy()
+    assert np_grad[0] == pytest.approx(float(th[0]), rel=1e-15)
+    assert np_grad[1] == pytest.approx(2.0 * float(th[1]), rel=1e-15)
+    assert np_grad[2] == pytest.approx(3.0 * float(th[2]), rel=1e-15)
+    e0 = mle.to_eta((1.5, 0.08, 0.0))
+    assert e0[2] == pytest.approx(np.log(mle.NUGGET_FLOOR))
+    back = mle.to_natural(torch.tensor(mle.to_eta((1.5, 0.08, 0.01)), dtype=torch.float64))
+    np.testing.assert_allclose(back.numpy(), [1.5, 0.08, 0.01], rtol=1e-14)
+    nu_eta = torch.tensor([0.0, 0.0, 0.0, 40.0], dtype=torch.float64)
+    nu = float(mle.to_natural(nu_eta, estimate_nu=True)[3])
+    assert mle.NU_LO < nu <= mle.NU_HI
