@@ -64,8 +64,9 @@ typedef enum {
  *   h = || (s_i - s_j) / aniso ||  (componentwise division; aniso = {1,1,1}
  *   is isotropic).  nu = 0.5, 1.5, 2.5 use the closed forms rho = e^-x,
  *   (1+x) e^-x, (1 + x + x^2/3) e^-x; any other nu in [0.05, 10] uses
- *   rho = 2^(1-nu)/Gamma(nu) x^nu K_nu(x), evaluated in FP64 (Temme's series,
- *   Steed's continued fraction, upward recurrence) by the one-wave kernels
+ *   rho = 2^(1-nu)/Gamma(nu) x^nu K_nu(x), evaluated in FP64 (Temme's series
+ *   for x <= 2, the trapezoidal rule on the integral representation of K for
+ *   x > 2, upward recurrence in the order) by the one-wave kernels
  *   only: other engines, blocks above VECCHIA_MAX_JOINT and the simulator
  *   return VECCHIA_EUNSUPPORTED for it, as for nu outside [0.05, 10].  The
  *   nugget applies to same-index pairs only (not to distinct points at
@@ -175,9 +176,13 @@ int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_t d, const 
  * VECCHIA_ENGINE_MFMA (default): each block's bordered joint matrix lives in
  *   16 x 16 matrix-core accumulator tiles of ONE wave (a 64-thread workgroup).
  *   The Cholesky runs in panels of four columns with rank-4 MFMA updates; the
- *   adjoint's back-substitution and contraction are MFMA products, 32
- *   right-hand sides per pass, so any l_i fits the LDS.  FP64 classes above
- *   G = 8 tile rows exceed the register file and spill part of the tiles.
+ *   adjoint's back-substitution and contraction are MFMA products.  Up to
+ *   G = 9 tile rows, when l_i + 2 right-hand sides fit one pass (28), the
+ *   factor stays in the registers through the adjoint (the inverses of its
+ *   diagonal tiles are formed during the factorisation); otherwise the factor
+ *   goes to the auxiliary tile buffer and the right-hand sides run in passes
+ *   of up to 32, so any l_i fits the LDS.  FP64 classes above G = 9 exceed the
+ *   register file and spill part of the tiles.
  * VECCHIA_ENGINE_MFMA_WG: the same tiles spread over the four waves of a
  *   workgroup, for every size class (two barriers per panel).
  * VECCHIA_ENGINE_TILES: one register tile per thread, one barrier per column
@@ -199,10 +204,12 @@ typedef enum { VECCHIA_ENGINE_MFMA = 0, VECCHIA_ENGINE_TILES = 1, VECCHIA_ENGINE
  * vecchia_loglik_grad returns VECCHIA_EUNSUPPORTED for them.
  * Auxiliary workspace: plan->aux_ws_bytes bytes (0 when not needed), attached
  * with vecchia_plan_attach_aux before the first evaluation, holds the large
- * blocks' matrices and, for engine MFMA, the adjoint's per-block factor tiles
- * (at most 4 GiB; the adjoint launches in chunks that fit it).  A smaller
+ * blocks' matrices and, for engine MFMA, the per-block factor tiles of the
+ * size classes whose adjoint goes through the tile buffer (at most 4 GiB;
+ * the adjoint launches in chunks that fit it).  A smaller
  * buffer is accepted down to the size that holds every large-block slot and
- * one work item's FP64 factor tiles of the largest one-wave class (else
+ * one work item's FP64 factor tiles of the largest class that uses the tile
+ * buffer (else
  * VECCHIA_ENOMEM): the size classes then run one after another, the adjoint
  * in as many launches as the buffer needs, and plan->aux_ws_bytes is lowered
  * to the attached size.  One plan's calls must not overlap in time (they

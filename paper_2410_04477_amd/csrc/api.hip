@@ -86,19 +86,20 @@ int theta_status(const vecchia_theta& t, int d, ThetaDev& o) {
   {
     // order-only constants of the Bessel form, also for the closed-form orders
     // (a launch that holds any other nu evaluates all its thetas that way):
-    // mu = nu - n, |mu| <= 1/2, Temme's Gamma1(mu) = (1/Gamma(1-mu) -
-    // 1/Gamma(1+mu)) / (2 mu) and Gamma2(mu) = their mean; for small mu,
-    // Gamma1 from the Taylor series of 1/Gamma(1+z) (Abramowitz and Stegun
-    // 6.1.34), which avoids the cancellation
-    o.nu_n = (int)floor(t.nu + 0.5);
-    const double mu = t.nu - o.nu_n;
-    o.nu_mu = mu;
-    o.nu_gampl = 1.0 / tgamma(1.0 + mu);
-    o.nu_gammi = 1.0 / tgamma(1.0 - mu);
-    o.nu_gam2 = 0.5 * (o.nu_gammi + o.nu_gampl);
-    o.nu_gam1 = fabs(mu) < 1e-3 ? -(0.5772156649015329 - 0.0420026350340952 * mu * mu)
-                                : (o.nu_gammi - o.nu_gampl) / (2.0 * mu);
-    o.nu_lognorm = (1.0 - t.nu) * log(2.0) - lgamma(t.nu);
+    // nu = n + mu with |mu| <= 1/2; for small mu, Gamma1 from the Taylor series
+    // of 1/Gamma(1 + z) (Abramowitz and Stegun 6.1.34), which avoids the
+    // cancellation of the difference quotient
+    BesselOrder& b = o.bes;
+    b.n = (int)floor(t.nu + 0.5);
+    const double mu = t.nu - b.n;
+    b.mu = mu;
+    b.gplus = tgamma(1.0 + mu);
+    b.gminus = tgamma(1.0 - mu);
+    const double rp = 1.0 / b.gplus, rm = 1.0 / b.gminus;
+    b.gam2 = 0.5 * (rm + rp);
+    b.gam1 = fabs(mu) < 1e-3 ? -(0.5772156649015329 - 0.0420026350340952 * mu * mu) : (rm - rp) / (2.0 * mu);
+    b.mu_pi_csc = fabs(mu) < 1e-14 ? 1.0 : M_PI * mu / sin(M_PI * mu);
+    b.lognorm = (1.0 - t.nu) * log(2.0) - lgamma(t.nu);
   }
   o.sigma2 = t.sigma2;
   o.nugget = t.nugget;
@@ -239,13 +240,13 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
     plan->aux_ws_bytes = (size_t)plan->large_slots * (size_t)(P * P) * sizeof(double);
   }
   if (engine == kEngineMfma && !predict) {
-    // adjoint factor tiles: every work item of the largest class, FP64, capped
+    // adjoint factor tiles, FP64, of every work item of the classes whose
+    // gradient goes through the tile buffer (the others keep the factor in
+    // registers), so that the classes can run concurrently; capped
     size_t need = 0;
     for (int c = 0; c < kMfmaMaxG; ++c)
-      if (hcounts[c] > 0 && wave_fits(c + 1, false)) {
-        const size_t b = (size_t)hcounts[c] * (size_t)max_theta * wave_tile_bytes(c + 1, false);
-        need = b > need ? b : need;
-      }
+      if (hcounts[c] > 0 && wave_fits(c + 1, false) && !wave_regadj(c + 1, false, hlmax[c]))
+        need += (size_t)hcounts[c] * (size_t)max_theta * wave_tile_bytes(c + 1, false);
     if (need > kAdjTileCap) need = kAdjTileCap;
     if (need > plan->aux_ws_bytes) plan->aux_ws_bytes = need;
   }
@@ -333,6 +334,10 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
   if (plan->engine == kEngineMfma && wave_fits(g, fp32)) {
     if (mode == 0) {
       VCHECK_HIP(launch_wave(g, fp32, 0, a, thp, grid, s));
+      return VECCHIA_OK;
+    }
+    if (wave_regadj(g, fp32, plan->bucket_lmax[q])) {   // no tile buffer needed
+      VCHECK_HIP(launch_wave(g, fp32, 5, a, thp, grid, s));
       return VECCHIA_OK;
     }
     // adjoint: as many work items per launch as its part of the tile buffer holds
@@ -513,7 +518,8 @@ static size_t aux_min_bytes(const vecchia_plan* plan) {
   if (plan->engine == kEngineMfma && plan->kind == 0)
     for (int q = 0; q < plan->nbuckets; ++q) {
       const int g = plan->bucket_cfg[q] + 1;
-      if (plan->bucket_cfg[q] != kLargeCfg && wave_fits(g, false) && wave_tile_bytes(g, false) > need)
+      if (plan->bucket_cfg[q] != kLargeCfg && wave_fits(g, false) && !wave_regadj(g, false, plan->bucket_lmax[q]) &&
+          wave_tile_bytes(g, false) > need)
         need = wave_tile_bytes(g, false);
     }
   return need;
@@ -574,23 +580,31 @@ static int check_common(const vecchia_plan* plan, const double* locs, const doub
   return VECCHIA_OK;
 }
 
-extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
-                              const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
-                              const vecchia_theta* theta, int32_t ntheta, int32_t precision, double* loglik,
-                              int32_t* counters, double* partial, void* stream) {
+int bv::check_loglik_args(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                          const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                          const vecchia_theta* theta, int32_t ntheta, int32_t precision, const double* loglik,
+                          bool need_aux) {
   int st = check_common(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision);
   if (st) return st;
   if (!loglik) return VECCHIA_EINVAL;
-  if (plan->aux_ws_bytes > 0 && !plan->aux_ws) return VECCHIA_ENOMEM;
+  if (need_aux && plan->aux_ws_bytes > 0 && !plan->aux_ws) return VECCHIA_ENOMEM;
+  return VECCHIA_OK;
+}
+
+// The value path of vecchia_loglik with its per-call buffers (per-block terms,
+// flags, compaction lists and counts) passed in; arguments already checked.
+int bv::loglik_run(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                   const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                   const vecchia_theta* theta, int32_t ntheta, int32_t precision, double* loglik,
+                   int32_t* counters, double* partial, const CallBuffers& cb, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   const int bc = (int)plan->bc;
-  void* ws = plan->ws;
   const bool fp32 = precision != VECCHIA_FP64;
-  const int* sched = at<int>(ws, plan->off_sched);
-  double* part = at<double>(ws, plan->off_partial);
-  int* flag = at<int>(ws, plan->off_flag);
-  int* list = at<int>(ws, plan->off_list);
-  int* count = at<int>(ws, plan->off_count);
+  const int* sched = at<int>(plan->ws, plan->off_sched);
+  double* part = cb.partial;
+  int* flag = cb.flag;
+  int* list = cb.list;
+  int* count = cb.count;
 
   for (int t0 = 0; t0 < ntheta; t0 += kMaxThetaPerLaunch) {
     const int nt = ntheta - t0 < kMaxThetaPerLaunch ? ntheta - t0 : kMaxThetaPerLaunch;
@@ -646,7 +660,7 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
       }
       FwdArgs r = a;
       r.fp32_guard = 0;
-      r.flag_or = 4;
+      r.flag_or = 5;   // re-run in FP64 (4); the guard bit (1) that listed it stays set
       for (int q = 0; q < plan->nbuckets; ++q) {
         const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
         r.list = list + plan->bucket_off[q] * nt;
@@ -667,6 +681,22 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
                                 hipMemcpyDeviceToDevice, s));
   }
   return VECCHIA_OK;
+}
+
+extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                              const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                              const vecchia_theta* theta, int32_t ntheta, int32_t precision, double* loglik,
+                              int32_t* counters, double* partial, void* stream) {
+  const int st = check_loglik_args(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision,
+                                   loglik, true);
+  if (st) return st;
+  CallBuffers cb;
+  cb.partial = at<double>(plan->ws, plan->off_partial);
+  cb.flag = at<int>(plan->ws, plan->off_flag);
+  cb.list = at<int>(plan->ws, plan->off_list);
+  cb.count = at<int>(plan->ws, plan->off_count);
+  return loglik_run(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision, loglik,
+                    counters, partial, cb, stream);
 }
 
 // ----------------------------------------------------------- loglik_grad --
@@ -718,8 +748,9 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
     for (int q = 0; q < plan->nbuckets; ++q) {
       const int g = plan->bucket_cfg[q] + 1;
       const size_t ns = (size_t)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
-      const bool wave = plan->engine == kEngineMfma && wave_fits(g, fp32);
-      off[q + 1] = off[q] + (wave ? ns * nt * wave_tile_bytes(g, fp32) : 0);
+      const bool tiles = plan->engine == kEngineMfma && plan->bucket_cfg[q] != kLargeCfg && wave_fits(g, fp32) &&
+                         !wave_regadj(g, fp32, plan->bucket_lmax[q]);
+      off[q + 1] = off[q] + (tiles ? ns * nt * wave_tile_bytes(g, fp32) : 0);
     }
     const bool conc = plan->exec != nullptr && off[plan->nbuckets] <= plan->aux_ws_bytes;
     // the largest class waits for the first factorisation launch of the split
@@ -768,7 +799,7 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
       }
       AdjArgs r = a;
       r.fp32_guard = 0;
-      r.flag_or = 4;
+      r.flag_or = 5;   // re-run in FP64 (4); the guard bit (1) that listed it stays set
       for (int q = 0; q < plan->nbuckets; ++q) {
         const int ns = (int)(plan->bucket_off[q + 1] - plan->bucket_off[q]);
         r.list = list + plan->bucket_off[q] * nt;

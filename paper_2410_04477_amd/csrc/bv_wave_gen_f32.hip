@@ -7,6 +7,7 @@ namespace bv {
 hipError_t launch_wave_gen_f32(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
   if (mode == 0) return launch_wave_t<float, 0, true>(g, a, thp, grid, s);
   if (mode == 1) return launch_wave_t<float, 1, true>(g, a, thp, grid, s);
+  if (mode == 5) return launch_wave_t<float, 5, true>(g, a, thp, grid, s);
   if (mode == 2) return launch_wave_t<float, 2, true>(g, a, thp, grid, s);
   if (mode == 3) return launch_wave_t<float, 3, true>(g, a, thp, grid, s);
   return hipErrorInvalidValue;

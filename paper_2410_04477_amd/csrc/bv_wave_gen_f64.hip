@@ -7,6 +7,7 @@ namespace bv {
 hipError_t launch_wave_gen_f64(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
   if (mode == 0) return launch_wave_t<double, 0, true>(g, a, thp, grid, s);
   if (mode == 1) return launch_wave_t<double, 1, true>(g, a, thp, grid, s);
+  if (mode == 5) return launch_wave_t<double, 5, true>(g, a, thp, grid, s);
   if (mode == 4) return launch_wave_t<double, 4, true>(g, a, thp, grid, s);
   return hipErrorInvalidValue;
 }

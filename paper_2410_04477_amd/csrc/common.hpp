@@ -11,6 +11,16 @@ namespace bv {
 constexpr int kMaxThetaPerLaunch = 24;   // theta values passed by value in kernel arguments
 constexpr double kLog2Pi = 1.83787706640934548356065947281123527;
 
+// Order-only constants of the Bessel form (host-computed per theta): the
+// order nu = n + mu with |mu| <= 1/2; Gamma(1 + mu), Gamma(1 - mu); Temme's
+// Gamma1(mu) = (1/Gamma(1 - mu) - 1/Gamma(1 + mu)) / (2 mu) and Gamma2(mu) =
+// (1/Gamma(1 - mu) + 1/Gamma(1 + mu)) / 2; mu pi / sin(mu pi); and
+// log(2^(1 - nu) / Gamma(nu)).
+struct BesselOrder {
+  double mu, gplus, gminus, gam1, gam2, mu_pi_csc, lognorm;
+  int n;
+};
+
 // One parameter vector as the kernels need it.  inv_scale[k] = 1 / (range * aniso[k]),
 // so the Matern argument is x = || (s_i - s_j) * inv_scale ||.
 struct ThetaDev {
@@ -19,100 +29,111 @@ struct ThetaDev {
   double inv_scale[3];
   double inv_range;   // 1 / range (gradient w.r.t. range)
   int nu_code;        // 0: nu = 1/2, 1: nu = 3/2, 2: nu = 5/2, 3: any other nu (Bessel form)
-  int nu_n;           // nu_code 3: nu = nu_n + nu_mu, |nu_mu| <= 1/2
-  // nu_code 3, order-only constants of the Bessel evaluation (host-computed):
-  // Temme's Gamma1(mu), Gamma2(mu), 1/Gamma(1 + mu), 1/Gamma(1 - mu), and
-  // log(2^(1 - nu) / Gamma(nu))
-  double nu_mu, nu_gam1, nu_gam2, nu_gampl, nu_gammi, nu_lognorm;
+  BesselOrder bes;    // nu_code 3: order-only constants of the Bessel form
 };
 
 struct ThetaPack {
   ThetaDev t[kMaxThetaPerLaunch];
 };
 
+// K_mu(x) and K_(mu+1)(x), |mu| <= 1/2, 0 < x <= 2: Temme's series (N. M.
+// Temme, J. Comput. Phys. 19 (1975) 324-337).  With c_k = (x^2/4)^k / k!,
+//   K_mu = sum_k c_k f_k,   K_(mu+1) = (2/x) sum_k c_k (p_k - k f_k),
+// where p_k, q_k are p_0 = Gamma(1 + mu) (x/2)^-mu / 2 and q_0 = Gamma(1 - mu)
+// (x/2)^mu / 2 divided by (1 - mu)..(k - mu) and (1 + mu)..(k + mu), and
+// f_k = (k f_(k-1) + p_(k-1) + q_(k-1)) / (k^2 - mu^2) starts from
+// f_0 = mu pi / sin(mu pi) [Gamma1 cosh(s) + Gamma2 ln(2/x) sinh(s) / s],
+// s = mu ln(2/x).  About 15 terms reach FP64 rounding on this range.
+__device__ inline void bessel_k_pair_series(double x, const BesselOrder& o, double& k_mu, double& k_mu1) {
+  const double log2x = log(2.0 / x);
+  const double s = o.mu * log2x;
+  const double sinhc = fabs(s) < 1e-14 ? 1.0 : sinh(s) / s;
+  const double es = exp(s);   // (2/x)^mu
+  double f = o.mu_pi_csc * (o.gam1 * cosh(s) + o.gam2 * log2x * sinhc);
+  double pk = 0.5 * o.gplus * es;
+  double qk = 0.5 * o.gminus / es;
+  const double quarter_x2 = 0.25 * x * x;
+  double ck = 1.0;
+  double sum_mu = f, sum_mu1 = pk;
+  for (int k = 1; k < 60; ++k) {
+    const double dk = (double)k;
+    const double dm = dk - o.mu, dp = dk + o.mu;
+    f = (dk * f + pk + qk) / (dm * dp);
+    pk /= dm;
+    qk /= dp;
+    ck *= quarter_x2 / dk;
+    const double t_mu = ck * f, t_mu1 = ck * (pk - dk * f);
+    sum_mu += t_mu;
+    sum_mu1 += t_mu1;
+    if (fabs(t_mu) <= 1e-17 * fabs(sum_mu) && fabs(t_mu1) <= 1e-17 * fabs(sum_mu1)) break;
+  }
+  k_mu = sum_mu;
+  k_mu1 = sum_mu1 * (2.0 / x);
+}
+
+// K_mu(x) and K_(mu+1)(x), |mu| <= 1/2, x > 2: the trapezoidal rule on the
+// integral representation K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt,
+// whose integrand is analytic and decays doubly exponentially, so the rule
+// converges geometrically in 1/h (L. N. Trefethen and J. A. C. Weideman,
+// SIAM Review 56 (2014) 385-458).  Step h = min(1/8, 0.7/sqrt(x)) keeps the
+// discretisation error below FP64 rounding for |v| <= 3/2 (the integrand's
+// width shrinks like 1/sqrt(x)); nodes are added until the integrand falls
+// below 1e-18 of the sum, at most 64 (13 to 31 on this range).  e^(+-v t) and
+// e^(+-t) advance by multiplication, so each node costs one exponential.
+__device__ inline void bessel_k_pair_quad(double x, double mu, double& k_mu, double& k_mu1) {
+  const double h = fmin(0.125, 0.7 * rsqrt(x));
+  const double a = exp(mu * h), ai = 1.0 / a, b = exp(h), bi = 1.0 / b;
+  double emu = 1.0, emui = 1.0, et = 1.0, eti = 1.0;   // e^(mu t), e^(-mu t), e^t, e^-t
+  double w = exp(-x);
+  double s_mu = 0.5 * w, s_mu1 = 0.5 * w;              // the t = 0 node carries weight 1/2
+  for (int k = 1; k < 64; ++k) {
+    emu *= a;
+    emui *= ai;
+    et *= b;
+    eti *= bi;
+    w = exp(-0.5 * x * (et + eti));
+    const double c1 = 0.5 * (emu * et + emui * eti);   // cosh((mu + 1) t)
+    s_mu += w * 0.5 * (emu + emui);
+    s_mu1 += w * c1;
+    if (w * c1 < 1e-18 * s_mu1) break;
+  }
+  k_mu = h * s_mu;
+  k_mu1 = h * s_mu1;
+}
+
 // Matern correlation for any nu > 0, eq. (maternkernel) with the modified
 // Bessel function of the second kind: rho(x) = 2^(1-nu)/Gamma(nu) x^nu K_nu(x),
-// in FP64.  K is evaluated at order mu = nu - n (|mu| <= 1/2) by Temme's series
-// (Temme 1975) for x <= 2 or Steed's continued fraction CF2 (Thompson and
-// Barnett 1987) for x > 2, each giving K_mu and K_(mu+1), then raised to order
-// nu by the forward recurrence K_(k+1) = 2k/x K_k + K_(k-1), which is stable for
-// K.  Also returns g = 2^(1-nu)/Gamma(nu) x^(nu+1) K_(nu-1)(x), from
-// d/dx [x^nu K_nu(x)] = -x^nu K_(nu-1)(x): d rho(h/range) / d range = g / range.
-// Not inlined: its loops would otherwise be copied into every generation site.
-__device__ __noinline__ inline void matern_general(double x, double mu, double gam1, double gam2, double gampl,
-                                                   double gammi, double lognorm, int n, double* rho, double* g) {
+// in FP64.  K at the reduced order mu, then raised to nu = n + mu by the
+// three-term recurrence K_(v+1) = K_(v-1) + (2 v / x) K_v, which is stable
+// upwards for K.  Also returns g = 2^(1-nu)/Gamma(nu) x^(nu+1) K_(nu-1)(x),
+// from d/dx [x^nu K_nu(x)] = -x^nu K_(nu-1)(x): d rho(h/range) / d range =
+// g / range.  Not inlined: its loops would otherwise be copied into every
+// generation site.
+__device__ __noinline__ inline void matern_general(double x, const BesselOrder& o, double* rho, double* g) {
   if (!(x > 0.0)) {
     *rho = 1.0;
     *g = 0.0;
     return;
   }
-  const double kEps = 1e-16, kPi = 3.14159265358979323846;
-  double km, kp;   // K_mu(x), K_(mu+1)(x)
-  if (x <= 2.0) {
-    // Temme: K_mu = sum c_k f_k, K_(mu+1) = (2/x) sum c_k (p_k - k f_k), c_k = (x^2/4)^k / k!
-    const double lx = -log(0.5 * x);   // ln(2/x)
-    const double sg = mu * lx;
-    const double fact = fabs(mu) < 1e-14 ? 1.0 : kPi * mu / sin(kPi * mu);
-    const double fact2 = fabs(sg) < 1e-14 ? 1.0 : sinh(sg) / sg;
-    double f = fact * (gam1 * cosh(sg) + gam2 * fact2 * lx);
-    const double es = exp(sg);
-    double p = 0.5 * es / gampl;    // (x/2)^-mu Gamma(1 + mu) / 2
-    double q = 0.5 / (es * gammi);  // (x/2)^mu Gamma(1 - mu) / 2
-    const double x24 = 0.25 * x * x;
-    double c = 1.0, s0 = f, s1 = p;
-    for (int k = 1; k < 200; ++k) {
-      const double dk = (double)k;
-      f = (dk * f + p + q) / (dk * dk - mu * mu);
-      c *= x24 / dk;
-      p /= dk - mu;
-      q /= dk + mu;
-      const double t0 = c * f;
-      s0 += t0;
-      s1 += c * (p - dk * f);
-      if (fabs(t0) < kEps * fabs(s0)) break;
+  double k_lo, k_hi;   // K_(v-1), K_v as v climbs from mu
+  {
+    double k_mu, k_mu1;
+    if (x <= 2.0)
+      bessel_k_pair_series(x, o, k_mu, k_mu1);
+    else
+      bessel_k_pair_quad(x, o.mu, k_mu, k_mu1);
+    // K_(mu-1) = K_(mu+1) - (2 mu / x) K_mu
+    k_lo = o.n == 0 ? k_mu1 - (2.0 * o.mu / x) * k_mu : k_mu;
+    k_hi = o.n == 0 ? k_mu : k_mu1;
+    for (int v = 1; v < o.n; ++v) {
+      const double next = k_lo + (2.0 * (o.mu + v) / x) * k_hi;
+      k_lo = k_hi;
+      k_hi = next;
     }
-    km = s0;
-    kp = s1 * (2.0 / x);
-  } else {
-    // Steed's algorithm for CF2: K_mu = sqrt(pi / 2x) e^-x / s
-    const double a1 = 0.25 - mu * mu;
-    double b = 2.0 * (1.0 + x), d = 1.0 / b, h = d, dh = d;
-    double q1 = 0.0, q2 = 1.0, q = a1, c = a1, a = -a1;
-    double s = 1.0 + q * dh;
-    for (int i = 2; i < 1000; ++i) {
-      a -= 2.0 * (i - 1);
-      c = -a * c / i;
-      const double qn = (q1 - b * q2) / a;
-      q1 = q2;
-      q2 = qn;
-      q += c * qn;
-      b += 2.0;
-      d = 1.0 / (b + a * d);
-      dh = (b * d - 1.0) * dh;
-      h += dh;
-      const double ds = q * dh;
-      s += ds;
-      if (fabs(ds) < kEps * fabs(s)) break;
-    }
-    km = sqrt(kPi / (2.0 * x)) * exp(-x) / s;
-    kp = km * (mu + x + 0.5 - a1 * h) / x;
   }
-  double kn, kn1;   // K_nu, K_(nu-1)
-  if (n == 0) {
-    kn = km;
-    kn1 = kp - (2.0 * mu / x) * km;   // K_(mu-1)
-  } else {
-    for (int k = 1; k < n; ++k) {
-      const double t = (2.0 * (mu + k) / x) * kp + km;
-      km = kp;
-      kp = t;
-    }
-    kn = kp;
-    kn1 = km;
-  }
-  const double nu = mu + n, lxn = log(x);
-  *rho = exp(lognorm + nu * lxn) * kn;
-  *g = exp(lognorm + (nu + 1.0) * lxn) * kn1;
+  const double nu = o.mu + o.n, logx = log(x);
+  *rho = exp(o.lognorm + nu * logx) * k_hi;
+  *g = exp(o.lognorm + (nu + 1.0) * logx) * k_lo;
 }
 
 template <typename T> __device__ __forceinline__ T expneg(T x);
@@ -164,12 +185,12 @@ template <typename T> struct MaternF<T, true> {
   __device__ __forceinline__ explicit MaternF(const ThetaDev& th) : t(th) {}
   __device__ __forceinline__ T rho(T x) const {
     double r, g;
-    matern_general((double)x, t.nu_mu, t.nu_gam1, t.nu_gam2, t.nu_gampl, t.nu_gammi, t.nu_lognorm, t.nu_n, &r, &g);
+    matern_general((double)x, t.bes, &r, &g);
     return T(r);
   }
   __device__ __forceinline__ void rho_drange(T x, T inv_range, T& r, T& dr) const {
     double rr, g;
-    matern_general((double)x, t.nu_mu, t.nu_gam1, t.nu_gam2, t.nu_gampl, t.nu_gammi, t.nu_lognorm, t.nu_n, &rr, &g);
+    matern_general((double)x, t.bes, &rr, &g);
     r = T(rr);
     dr = T(g) * inv_range;
   }

@@ -81,6 +81,17 @@ constexpr size_t kAdjTileCap = (size_t)4 << 30;
 bool wave_fits(int g, bool fp32);
 // gradient as two launches (factor + tiles, then the adjoint from the tiles)
 inline bool wave_split(int g, bool fp32) { return fp32 && g >= 10; }
+// gradient in one launch with the factor kept in the registers (no tile
+// buffer): classes up to G = 9 whose right-hand sides (l_max + 2) fit one pass
+#ifndef BV_REGADJ_MAX_G32
+#define BV_REGADJ_MAX_G32 9
+#endif
+#ifndef BV_REGADJ_MAX_G64
+#define BV_REGADJ_MAX_G64 9
+#endif
+inline bool wave_regadj(int g, bool fp32, int lmax) {
+  return g >= 1 && g <= (fp32 ? BV_REGADJ_MAX_G32 : BV_REGADJ_MAX_G64) && lmax + 2 <= wave_chunk(g);
+}
 // prediction: round the conditioning-set size up to the factorisation's panel width
 __host__ __device__ constexpr int pred_rows(int m) { return (m + 3) & ~3; }
 hipError_t launch_wave_f32(int g, int mode, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
@@ -130,5 +141,25 @@ hipError_t launch_compact_flagged(const int* sched, int nsched, int ntheta, int 
 hipError_t launch_reduce_partials(const double* partial, const int* flag, int bc, int ntheta, int fp64_only,
                                   double* out, int* counters, hipStream_t s);
 hipError_t launch_reduce_vec(const double* vec, int bc, int k, int ntheta, double* out, hipStream_t s);
+
+// Per-call device buffers of the value path (the plan's workspace, or the
+// static array of vecchia_loglik_noalloc): partial and flag hold
+// ntheta * bc entries, list ntheta * bc, count one per size class.
+struct CallBuffers {
+  double* partial;
+  int* flag;
+  int* list;
+  int* count;
+};
+// Argument checks of vecchia_loglik (need_aux: the plan's auxiliary workspace
+// must be attached when it has one).
+int check_loglik_args(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                      const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                      const vecchia_theta* theta, int32_t ntheta, int32_t precision, const double* loglik,
+                      bool need_aux);
+int loglik_run(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+               const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+               const vecchia_theta* theta, int32_t ntheta, int32_t precision, double* loglik,
+               int32_t* counters, double* partial, const CallBuffers& cb, void* stream);
 
 }  // namespace bv

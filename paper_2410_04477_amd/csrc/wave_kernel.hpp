@@ -110,6 +110,9 @@ constexpr int wave_min_waves() { return sizeof(T) == 4 && (G <= 9 || MODE == 3) 
 // carries y_N and zeros, and only the neighbour columns are eliminated, which
 // leaves the Schur complement -- the conditional covariance of the block and,
 // in the border row, minus its conditional mean -- in the trailing tiles.
+// 5 value and gradient in one launch with the factor kept in the registers
+// through the back-substitution (no tile buffer; one pass of right-hand sides,
+// l + 2 <= wave_chunk(G)).
 // GEN: covariances by the Bessel form for any nu instead of the closed forms.
 template <typename T, int G, int MODE, bool GEN>
 __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
@@ -120,7 +123,10 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   extern __shared__ __align__(16) unsigned char smem[];
   T* su = reinterpret_cast<T*>(smem);  // scaled coordinates relative to the block's first point, su[k * P + i]
   T* work = su + 3 * P;
-  T* sy = work + 4 * P;                // border row y_J
+  // MODE 5 appends 16 rows to the panel (the identity rows whose elimination
+  // gives the inverse of each diagonal tile of the factor)
+  constexpr int PS = MODE == 5 ? P + 16 : P;   // panel column stride
+  T* sy = work + 4 * PS;               // border row y_J
   T* sdk = sy + P;                     // pivots d_k
   T* swk = sdk + P;                    // border entries w_k
 
@@ -173,11 +179,11 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   double acc_ll = 0.0;
   int flag = 0;
   const MaternF<T, GEN> mc(th);
+  acc_t acc[NT];   // the bordered matrix, then its factor (unused by MODE 3)
   if constexpr (MODE != 3) {   // MODE 3 starts from the factor tiles of a MODE 2 launch
 
   // ---- generate the bordered joint matrix in the accumulator tiles ----------
   const T sig2 = T(th.sigma2), nug = T(th.nugget);
-  acc_t acc[NT];
   static_for<0, G>(BV_CI(I) {
     BV_CV(I);
     T ri[4][3];
@@ -214,7 +220,14 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   });
 
   // ---- factorisation, four columns per step -----------------------------------
-  T* pan = work;  // pan[c * P + row], c < 4
+  T* pan = work;  // pan[c * PS + row], c < 4
+  // MODE 5: the 16 rows appended below the matrix while tile column K is
+  // eliminated, R = e_j^T at column 16 K + j (zero left of the tile column,
+  // so earlier columns leave them untouched).  After the tile column they hold
+  // R L_KK^-T = L_KK^-T, and the transpose of that, inv(L_KK), replaces L_KK
+  // in the tiles (nothing in the factorisation reads L_KK afterwards).  Held
+  // negated like the matrix tiles.
+  acc_t einv;
   // columns c0 .. c0 + 3 of tile column Kc to the panel
   auto publish = [&](auto Kc_c, int c0) __attribute__((always_inline)) {
     constexpr int Kc = decltype(Kc_c)::value;
@@ -222,8 +235,12 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       static_for<Kc, G>(BV_CI(I) {
         BV_CV(I);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) pan[(lr - c0) * P + I * 16 + M::row(lg, r)] = acc[tix(I, Kc)][r];
+        for (int r = 0; r < 4; ++r) pan[(lr - c0) * PS + I * 16 + M::row(lg, r)] = acc[tix(I, Kc)][r];
       });
+      if (MODE == 5) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) pan[(lr - c0) * PS + P + M::row(lg, r)] = einv[r];
+      }
     }
   };
   // the panel at column k0: 4 x 4 diagonal block (same values in every lane),
@@ -234,7 +251,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 #pragma unroll
     for (int c = 0; c < 4; ++c)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Ld[r][c] = r >= c ? -pan[c * P + k0 + r] : T(0);   // panel holds -A
+      for (int r = 0; r < 4; ++r) Ld[r][c] = r >= c ? -pan[c * PS + k0 + r] : T(0);   // panel holds -A
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const bool real = k0 + c < p;
@@ -255,24 +272,25 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     }
     const int i0 = k0 & ~15;
 #pragma unroll
-    for (int q = 0; q < (P + 63) / 64; ++q) {
+    for (int q = 0; q < (PS + 63) / 64; ++q) {
       const int i = i0 + ln + 64 * q;
-      if (i < P) {
+      if (i < PS) {
         // branch-free: every lane runs the substitution, which also yields the
         // rows of the diagonal block up to their diagonal (the operations that
-        // formed Ld); right of the diagonal there, and above the block, is zero
-        const int di = i - k0;
+        // formed Ld); right of the diagonal there, and above the block, is zero.
+        // An appended row j stands for column i0 + j: identity at the padding.
+        const int di = (i < P ? i : i0 + (i - P)) - k0;
         T x[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          T v = -pan[c * P + i];
+          T v = -pan[c * PS + i];
 #pragma unroll
           for (int j = 0; j < c; ++j) v -= x[j] * Ld[c][j];
-          const T t = di < c ? T(0) : v * rinv[c];
+          const T t = di < c && i < P ? T(0) : v * rinv[c];
           x[c] = (k0 + c < p) ? t : (di == c ? T(1) : T(0));   // padding columns: identity
         }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) pan[c * P + i] = x[c];
+        for (int c = 0; c < 4; ++c) pan[c * PS + i] = x[c];
         if (i == p) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) swk[k0 + c] = x[c];
@@ -281,7 +299,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     }
     if (ln == 0) {
 #pragma unroll
-      for (int c = 0; c < 4; ++c) sdk[k0 + c] = piv[c];
+      for (int c = 0; c < 4; ++c) {
+        sdk[k0 + c] = piv[c];
+      }
     }
   };
 
@@ -289,6 +309,14 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   static_for<0, G>(BV_CI(K) {
     BV_CV(K);
     if (K * 16 >= kend) return;
+    if constexpr (MODE == 5) {
+      // -e_j for the columns the loop below eliminates; columns it skips (at
+      // and beyond kend: the border column and the padding) keep +e_j, the
+      // identity of the inverse there
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        einv[r] = M::row(lg, r) == lr ? (K * 16 + lr < kend ? T(-1) : T(1)) : T(0);
+    }
 #pragma nounroll
     for (int c0 = 0; c0 < 16; c0 += 4) {
       const int k0 = K * 16 + c0;
@@ -300,7 +328,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       T v[G];
       static_for<K, G>(BV_CI(I) {
         BV_CV(I);
-        v[I] = pan[lg * P + I * 16 + lr];
+        v[I] = pan[lg * PS + I * 16 + lr];
       });
       static_for<K, G>(BV_CI(I) {
         BV_CV(I);
@@ -309,14 +337,28 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
           acc[tix(I, J)] = M::op(v[I], v[J], acc[tix(I, J)]);
         });
       });
+      if (MODE == 5) einv = M::op(pan[lg * PS + P + lr], v[K], einv);
       if (MODE != 0 && MODE != 4 && lr >= c0 && lr < c0 + 4) {
         // keep the finished factor columns in the tiles
         static_for<K, G>(BV_CI(I) {
           BV_CV(I);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) acc[tix(I, K)][r] = pan[(lr - c0) * P + I * 16 + M::row(lg, r)];
+          for (int r = 0; r < 4; ++r) acc[tix(I, K)][r] = pan[(lr - c0) * PS + I * 16 + M::row(lg, r)];
         });
+        if (MODE == 5) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) einv[r] = pan[(lr - c0) * PS + P + M::row(lg, r)];
+        }
       }
+      __syncthreads();
+    }
+    if constexpr (MODE == 5) {
+      // inv(L_KK) = (L_KK^-T)^T into the diagonal tile, transposed through LDS
+#pragma unroll
+      for (int r = 0; r < 4; ++r) pan[lr * 16 + M::row(lg, r)] = einv[r];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[tix(K, K)][r] = pan[M::row(lg, r) * 16 + lr];
       __syncthreads();
     }
   });
@@ -384,15 +426,17 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     }
   }
   if (MODE == 0) return;
-  // the factor leaves the registers for this item's slot of the tile buffer
-  // (accumulator order, 256 elements per tile), so the adjoint's phases do not
-  // hold the tiles in registers
-  static_for<0, NT>(BV_CI(t) {
-    BV_CV(t);
+  if constexpr (MODE != 5) {
+    // the factor leaves the registers for this item's slot of the tile buffer
+    // (accumulator order, 256 elements per tile), so the adjoint's phases do not
+    // hold the tiles in registers
+    static_for<0, NT>(BV_CI(t) {
+      BV_CV(t);
 #pragma unroll
-    for (int r = 0; r < 4; ++r) Lg[t * 256 + ln * 4 + r] = acc[t][r];
-  });
-  __syncthreads();
+      for (int r = 0; r < 4; ++r) Lg[t * 256 + ln * 4 + r] = acc[t][r];
+    });
+    __syncthreads();
+  }
   if (MODE == 2) return;
   } else {
     flag = a.flag[o];   // written by the factorisation launch
@@ -409,6 +453,159 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   const int Gp = (p + 15) >> 4;
   T* X = work;   // X[row * LDX + col], one chunk of right-hand sides
 
+  const T irange = T(th.inv_range);
+  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  // W = alpha alpha^T - b b^T - X_R X_R^T over the right-hand sides [cb, cb + nc)
+  // held in X, contracted with dK regenerated entry by entry
+  auto contract = [&](int cb, int nc) __attribute__((always_inline)) {
+    // the next tile's MFMA chain is issued before this tile's contraction
+    const int nk = (nc + 3) >> 2;
+    for (int I = 0; I < Gp; ++I) {
+      T av[CH / 4];
+#pragma unroll
+      for (int kq = 0; kq < CH / 4; ++kq) {
+        const int q = 4 * kq + lg;
+        av[kq] = (cb + q == 0 ? T(1) : T(-1)) * X[(I * 16 + lr) * LDX + q];
+      }
+      T ri[4][3];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = I * 16 + M::row(lg, r);
+        ri[r][0] = su[i];
+        ri[r][1] = su[P + i];
+        ri[r][2] = su[2 * P + i];
+      }
+      auto wtile = [&](int J) __attribute__((always_inline)) {
+        acc_t c;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) c[r] = T(0);
+#pragma unroll
+        for (int kq = 0; kq < CH / 4; ++kq)
+          if (kq < nk) c = M::op(av[kq], X[(J * 16 + lr) * LDX + 4 * kq + lg], c);
+        return c;
+      };
+      acc_t cn = wtile(0);
+      for (int J = 0; J <= I; ++J) {
+        const acc_t c = cn;
+        if (J < I) cn = wtile(J + 1);
+        const int j = J * 16 + lr;
+        const T sj0 = su[j], sj1 = su[P + j], sj2 = su[2 * P + j];
+        T s0 = T(0), s1 = T(0), s2 = T(0);
+        auto entry = [&](int r) __attribute__((always_inline)) {
+          const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
+          const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
+          T rho, drho;
+          mc.rho_drange(x, irange, rho, drho);
+          s0 += c[r] * rho;
+          s1 += c[r] * drho;
+        };
+        if ((I + 1) * 16 <= p) {   // a tile inside the point rows (wave-uniform)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) entry(r);
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (I * 16 + M::row(lg, r) < p && j < p) entry(r);
+        }
+        if (I == J) {   // d K / d nugget is the identity
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (M::row(lg, r) == lr && j < p) s2 += c[r];
+        }
+        const double wgt = I == J ? 1.0 : 2.0;
+        g0 += wgt * (double)s0;
+        g1 += wgt * (double)s1;
+        g2 += (double)s2;
+      }
+    }
+  };
+
+  if constexpr (MODE == 5) {
+    // ---- factor kept in the registers (its diagonal tiles already replaced by
+    // their inverses): one pass of right-hand sides -------------------------
+    // border row of the bordered factor, w = L^-1 y_J, from the factorisation's
+    // LDS record (read before the right-hand sides below overwrite it)
+    constexpr int NW = (P + 63) / 64;
+    T wreg[NW];
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int j = ln + 64 * k;
+      wreg[k] = j < p ? swk[j] : T(0);
+    }
+    __syncthreads();
+    // right-hand sides [ w | [z; 0] | [0; I_l] ] (nr <= CH: one pass)
+    const int nq = (nr + 15) >> 4;
+    for (int e = ln; e < P * LDX + 32; e += 64) X[e] = T(0);
+    __syncthreads();
+    for (int c = ln; c < nr; c += 64)
+      if (c >= 2) X[(m + c - 2) * LDX + c] = T(1);
+#pragma unroll
+    for (int k = 0; k < NW; ++k) {
+      const int j = ln + 64 * k;
+      if (j < p) {
+        X[j * LDX] = wreg[k];
+        if (j < m) X[j * LDX + 1] = wreg[k];
+      }
+    }
+    __syncthreads();
+    // X <- L^-T X, tile row by tile row from the bottom.  Every product
+    // contracts over the rows of a factor tile, so the accumulator registers
+    // serve as the A operand as they are: k-step s of lane (i, k) takes
+    // register s, i.e. row M::row(k, s) of the tile, and the B operand takes
+    // the same row of X.  The diagonal step's result, in accumulator layout,
+    // is then directly the B operand of the updates of the rows above.
+    static_for_down<0, G>(BV_CI(K) {
+      BV_CV(K);
+      if (K >= Gp) return;
+      acc_t dq[2];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dq[q][r] = T(0);
+        if (q < nq) {
+          T xb[4];
+#pragma unroll
+          for (int sb = 0; sb < 4; ++sb) xb[sb] = X[(K * 16 + M::row(lg, sb)) * LDX + q * 16 + lr];
+#pragma unroll
+          for (int sb = 0; sb < 4; ++sb) dq[q] = M::op(acc[tix(K, K)][sb], xb[sb], dq[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (q < nq && (q == 0 || colok)) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) X[(K * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = dq[q][r];
+        }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) dq[q][r] = -dq[q][r];
+      // rows above: X_J -= L_KJ^T X_K
+      static_for<0, K>(BV_CI(J) {
+        BV_CV(J);
+        acc_t cj[2];
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (q < nq) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cj[q][r] = X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr];
+          }
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            if (q < nq) cj[q] = M::op(acc[tix(K, J)][sb], dq[q][sb], cj[q]);
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+          if (q < nq && (q == 0 || colok)) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = cj[q][r];
+          }
+      });
+      __syncthreads();
+    });
+    contract(0, nr);
+  } else {
   // border row p of the bordered factor: w = L^-1 y_J (read before the
   // diagonal tiles are replaced by their inverses)
   constexpr int NW = (P + 63) / 64;
@@ -468,8 +665,6 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   __syncthreads();
 
   // ---- X <- L^-T X and the contraction, CH right-hand sides per pass ---------
-  const T irange = T(th.inv_range);
-  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
   for (int cb = 0; cb < nr; cb += CH) {
     const int nc = nr - cb < CH ? nr - cb : CH;
     const int nq = (nc + 15) >> 4;
@@ -561,68 +756,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       }
     }
 
-    // W = alpha alpha^T - b b^T - X_R X_R^T (this chunk's columns), contracted with dK;
-    // the next tile's MFMA chain is issued before this tile's contraction
-    const int nk = (nc + 3) >> 2;
-    for (int I = 0; I < Gp; ++I) {
-      T av[CH / 4];
-#pragma unroll
-      for (int kq = 0; kq < CH / 4; ++kq) {
-        const int q = 4 * kq + lg;
-        av[kq] = (cb + q == 0 ? T(1) : T(-1)) * X[(I * 16 + lr) * LDX + q];
-      }
-      T ri[4][3];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = I * 16 + M::row(lg, r);
-        ri[r][0] = su[i];
-        ri[r][1] = su[P + i];
-        ri[r][2] = su[2 * P + i];
-      }
-      auto wtile = [&](int J) __attribute__((always_inline)) {
-        acc_t c;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) c[r] = T(0);
-#pragma unroll
-        for (int kq = 0; kq < CH / 4; ++kq)
-          if (kq < nk) c = M::op(av[kq], X[(J * 16 + lr) * LDX + 4 * kq + lg], c);
-        return c;
-      };
-      acc_t cn = wtile(0);
-      for (int J = 0; J <= I; ++J) {
-        const acc_t c = cn;
-        if (J < I) cn = wtile(J + 1);
-        const int j = J * 16 + lr;
-        const T sj0 = su[j], sj1 = su[P + j], sj2 = su[2 * P + j];
-        T s0 = T(0), s1 = T(0), s2 = T(0);
-        auto entry = [&](int r) __attribute__((always_inline)) {
-          const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
-          const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
-          T rho, drho;
-          mc.rho_drange(x, irange, rho, drho);
-          s0 += c[r] * rho;
-          s1 += c[r] * drho;
-        };
-        if ((I + 1) * 16 <= p) {   // a tile inside the point rows (wave-uniform)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) entry(r);
-        } else {
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (I * 16 + M::row(lg, r) < p && j < p) entry(r);
-        }
-        if (I == J) {   // d K / d nugget is the identity
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (M::row(lg, r) == lr && j < p) s2 += c[r];
-        }
-        const double wgt = I == J ? 1.0 : 2.0;
-        g0 += wgt * (double)s0;
-        g1 += wgt * (double)s1;
-        g2 += (double)s2;
-      }
-    }
+    contract(cb, nc);
   }
+  }   // MODE != 5
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     g0 += __shfl_down(g0, off, 64);
@@ -631,7 +767,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   }
   if (ln == 0) {
     const bool bad = (flag & 2) && !a.fp32_guard;
-    if (MODE == 1) {
+    if (MODE == 1 || MODE == 5) {
       a.partial[o] = bad ? __builtin_nan("") : -0.5 * (acc_ll + (double)l * kLog2Pi);
       a.flag[o] = flag | a.flag_or;
     }
@@ -650,7 +786,20 @@ static hipError_t launch_wave_g(const AdjArgs& a, const ThetaPack& thp, int grid
 
 template <typename T, int MODE, bool GEN = false>
 static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
-  if constexpr (MODE == 2 || MODE == 3) {   // split gradient: only the classes that use it
+  if constexpr (MODE == 5) {   // factor kept in the registers: up to G = 9
+    switch (g) {
+      case 1: return launch_wave_g<T, 1, MODE, GEN>(a, thp, grid, s);
+      case 2: return launch_wave_g<T, 2, MODE, GEN>(a, thp, grid, s);
+      case 3: return launch_wave_g<T, 3, MODE, GEN>(a, thp, grid, s);
+      case 4: return launch_wave_g<T, 4, MODE, GEN>(a, thp, grid, s);
+      case 5: return launch_wave_g<T, 5, MODE, GEN>(a, thp, grid, s);
+      case 6: return launch_wave_g<T, 6, MODE, GEN>(a, thp, grid, s);
+      case 7: return launch_wave_g<T, 7, MODE, GEN>(a, thp, grid, s);
+      case 8: return launch_wave_g<T, 8, MODE, GEN>(a, thp, grid, s);
+      case 9: return launch_wave_g<T, 9, MODE, GEN>(a, thp, grid, s);
+      default: return hipErrorInvalidValue;
+    }
+  } else if constexpr (MODE == 2 || MODE == 3) {   // split gradient: only the classes that use it
     if (g == 10) return launch_wave_g<T, 10, MODE, GEN>(a, thp, grid, s);
     if (g == 11) return launch_wave_g<T, 11, MODE, GEN>(a, thp, grid, s);
     return hipErrorInvalidValue;

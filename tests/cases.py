@@ -35,6 +35,7 @@ def problem(name: str, n: int, d: int, bc: int, m: int, theta: W.Theta, seed: in
                 wscale=wscale, theta=theta, n=n, d=d)
 
 
+@functools.lru_cache(maxsize=4)
 def workload_problem(w: W.Workload, ysim: str = "block", kmeans_iters: int = 30):
     """A configured workload with the oracle's own preprocessing."""
     s = W.locations(w)

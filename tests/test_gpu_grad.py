@@ -179,6 +179,49 @@ def test_c4_full_size_gradient_vs_oracle():
               f"{np.array2string(np.abs(g32[i].cpu().numpy() - ref) / scale, precision=2)}")
 
 
+@pytest.mark.parametrize("engine", ENGINES)
+def test_value_of_gradient_call_on_a_fresh_plan(engine):
+    """vecchia_loglik_grad on a plan that never ran vecchia_loglik: its values
+    (total and per block) come from the gradient kernels alone and equal the
+    oracle's, in FP64 and FP32-bulk, for classes that keep the factor in
+    registers and classes that go through the tile buffer."""
+    th = W.Theta(1.2, 0.07, 3e-3, 1.5)
+    for m, bc in ((40, 400), (120, 150)):
+        pb = problem(f"fresh{m}", 3000, 2, bc, m, th, 55 + m, ysim="exact")
+        ref = oracle_terms(pb, th)
+        for prec, tol in (("fp64", 1e-8), ("fp32", 1e-4)):
+            mod = _model(pb, 1.5, engine=engine)
+            ll, _, _, part, _ = mod.loglik_grad([mod.theta(th.sigma2, th.beta, th.nugget)], prec, want_partial=True)
+            assert abs(float(ll[0]) - ref.sum()) <= tol * abs(ref.sum()), (m, prec, float(ll[0]), ref.sum())
+            if prec == "fp64":
+                np.testing.assert_allclose(part[0].cpu().numpy(), ref, rtol=1e-8, atol=1e-9)
+
+
+def test_c4_full_size_mle_end_point_judged_by_oracle():
+    """n = 200,000, 20,000 blocks, m = 100: L-BFGS from theta0 = (1, 0.05, 0.05)
+    with the FP64 adjoint, then the oracle's own gradient at the end point:
+    stationary to 1e-3 of the cancellation-free scale sum_i |dl_i| per
+    component, and the oracle's log-likelihood there at least its value at
+    the generating theta."""
+    from paper_2410_04477_amd import mle
+    w = W.C4
+    pb = workload_problem(w, ysim="block")
+    mod = _model(pb, 1.5)
+    res = mle.fit(mod, W.C4_THETA0, "fp64", max_evals=120)
+    th_hat = W.Theta(*res.theta, 1.5)
+    terms = _oracle_grad(pb, th_hat)
+    g, scale = terms.sum(0), np.abs(terms).sum(0)
+    args = (pb["locs_perm"], pb["y_perm"], pb["block_ptr"], pb["nbr_ptr"], pb["nbr_idx"])
+    ll_hat, ll_true = coracle.loglik(*args, th_hat), coracle.loglik(*args, w.theta)
+    ll0 = coracle.loglik(*args, W.Theta(*W.C4_THETA0, 1.5))
+    print(f"C4 MLE: theta {np.array2string(np.asarray(res.theta), precision=5)} after {res.evals} evaluations "
+          f"({res.seconds:.2f} s); oracle l: start {ll0:.3f}, truth {ll_true:.3f}, end {ll_hat:.3f}; "
+          f"gradient / sum|dl_i| {np.array2string(np.abs(g) / scale, precision=2)}", flush=True)
+    assert abs(res.loglik - ll_hat) <= 1e-8 * abs(ll_hat)
+    assert ll_hat >= ll_true and ll_hat > ll0
+    assert np.all(np.abs(g) <= 1e-3 * scale), (g, scale)
+
+
 def test_simulator_matches_oracle():
     from paper_2410_04477_amd import api
     from oracle.preprocess import point_neighbors
