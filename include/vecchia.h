@@ -304,6 +304,33 @@ int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm, const doub
                    const vecchia_theta* theta, int32_t ntheta, int32_t precision,
                    double* loglik, int32_t* counters, double* partial, void* stream);
 
+/* -------------------------------------------------------- loglik_noalloc --
+ * For callers that cannot allocate device memory at call time (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * value path of vecchia_loglik, same arguments and results bit for bit, but
+ * the per-call buffers (per-block terms, guard flags, the FP64 re-run list and
+ * its counters) live in a static device array of the library instead of the
+ * plan's workspace.  The call itself allocates nothing.
+ *   - The array holds VECCHIA_NOALLOC_SCRATCH_BYTES bytes (about 16 MiB) on
+ *     each GPU the library runs on, until the process ends; its device
+ *     address is resolved once per device by vecchia_plan_init (or by the
+ *     first call on that device).
+ *   - plan->bc * ntheta above VECCHIA_NOALLOC_MAX_ITEMS: VECCHIA_ENOMEM.
+ *   - Plans with blocks above VECCHIA_MAX_JOINT: VECCHIA_EUNSUPPORTED (those
+ *     blocks are factored in the auxiliary workspace).  No auxiliary
+ *     workspace is needed otherwise.
+ *   - Every call on one GPU uses that GPU's one array: calls that overlap in
+ *     time on the same GPU (other streams, other threads, other plans) race
+ *     and must be serialised by the caller.  The plan's workspace still
+ *     provides the block schedule (read only). */
+#define VECCHIA_NOALLOC_MAX_ITEMS (1 << 20)
+#define VECCHIA_NOALLOC_SCRATCH_BYTES ((size_t)16777472)
+size_t vecchia_noalloc_scratch_bytes(void);
+int vecchia_loglik_noalloc(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                           const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                           const vecchia_theta* theta, int32_t ntheta, int32_t precision,
+                           double* loglik, int32_t* counters, double* partial, void* stream);
+
 /* ----------------------------------------------------------- loglik_grad --
  * Log-likelihood and its gradient w.r.t. (sigma2, range, nugget) for each
  * theta.  The gradient is the adjoint of the per-block chain of Alg. 1,

@@ -16,6 +16,7 @@ PLAN_PREDICT = 16
 ORDER_MORTON, ORDER_MAXMIN, ORDER_HILBERT, ORDER_KDTREE = 1, 2, 3, 4
 
 OK, EINVAL, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4
+NOALLOC_MAX_ITEMS = 1 << 20
 FP64, FP32_BULK = 0, 1
 
 
@@ -58,6 +59,8 @@ SIGNATURES = {
     "vecchia_plan_workspace_size": (SZ, [I64, I32]),
     "vecchia_plan_init": (ctypes.c_int, [P, P, P, I64, I64, I32, I32, P, SZ, P]),
     "vecchia_loglik": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P]),
+    "vecchia_loglik_noalloc": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P]),
+    "vecchia_noalloc_scratch_bytes": (SZ, []),
     "vecchia_permute": (ctypes.c_int, [P, I64, I32, P, P, P]),
     "vecchia_loglik_grad": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P, P, P]),
     "vecchia_loglik_dnu": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, ctypes.c_double, P, P, P]),

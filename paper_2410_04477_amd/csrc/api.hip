@@ -276,6 +276,10 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
   plan->off_grad = L.grad;
   plan->engine = engine;
   plan->kind = predict ? 1 : 0;
+  // the static array of vecchia_loglik_noalloc: its device address on this
+  // device is resolved here, at set-up, rather than inside a later call (a
+  // failure is reported by that entry point)
+  (void)noalloc_prepare_current_device();
   int dev = 0, lds = 0;
   VCHECK_HIP(hipGetDevice(&dev));
   VCHECK_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));

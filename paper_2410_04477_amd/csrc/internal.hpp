@@ -161,5 +161,8 @@ int loglik_run(const vecchia_plan* plan, const double* locs_perm, const double* 
                const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
                const vecchia_theta* theta, int32_t ntheta, int32_t precision, double* loglik,
                int32_t* counters, double* partial, const CallBuffers& cb, void* stream);
+// Resolves, once per device, the device address of the static array behind
+// vecchia_loglik_noalloc, for the current device.
+int noalloc_prepare_current_device();
 
 }  // namespace bv
