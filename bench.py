@@ -193,9 +193,7 @@ def main() -> int:
         fq = float(np.sum(step_flops(psz[blk].astype(np.float64), msz[blk].astype(np.float64),
                                      lsz[blk].astype(np.float64))))
         flops_launch += fq
-        R, G = api.tile_config(cfg, plan.engine)
-        kn = {"mfma": f"bv_wave_kernel<float,{G},1>", "mfma_wg": f"bv_mfma_kernel<float,{G},1>"}.get(
-            plan.engine, f"bv_adj_kernel<float,{R},{G},0>")
+        kn = plan.class_kernel(q, "fp32", True)
         names.append(kn)
         cls.append({"kernel": kn, "blocks": int(nb), "flops": fq, "ms_per_step": kt[q][0] / args.steps})
     achieved = flops_launch / avg_span_s
@@ -210,8 +208,7 @@ def main() -> int:
             traffic = float(sum(tr[n]["bytes_per_launch"] for n in names))
     roofline = {"bound": "alu" if plan.engine == "tiles" else "mfma", "achieved": achieved / 1e12,
                 "peak": FP32_PEAK / 1e12, "unit": "TFLOP/s", "frac": achieved / FP32_PEAK, "traffic": traffic,
-                "kernel": f"{names[0].split('<')[0]}<float,G,...> over {len(names)} concurrent size classes "
-                          f"({', '.join(names)})",
+                "kernel": f"{len(names)} concurrent size classes ({', '.join(names)})",
                 "launch": "span of one call's concurrent size-class launches (first start to last end)",
                 "avg_launch_ms": avg_span_s * 1e3, "flops_per_launch": flops_launch,
                 "blocks_per_launch": int(sum(c["blocks"] for c in cls)),
@@ -230,10 +227,10 @@ def main() -> int:
             wv, _, ktv = timed(prec, grad, k2, 1, with_timing=True)
             key = f"{prec}_{'loglik_grad' if grad else 'loglik'}"
             variants[f"{key}_evals_per_s"] = k2 / wv
-            tname = "double" if prec == "fp64" else "float"
+            vnames = [plan.class_kernel(q, prec, grad) for q in range(len(classes))]
             variants[f"{key}_roofline"] = span_roofline(
                 ktv, len(classes), flops_launch if grad else flops_value, FP64_PEAK if prec == "fp64" else FP32_PEAK,
-                f"bv_wave_kernel<{tname},G,{1 if grad else 0}> over {len(classes)} concurrent size classes")
+                f"{len(classes)} concurrent size classes ({', '.join(vnames)})")
         variants["fp32_loglik_grad_evals_per_s"] = evals
         variants["speedup_fp32_over_fp64_loglik_grad"] = evals / variants["fp64_loglik_grad_evals_per_s"]
         variants["speedup_fp32_over_fp64_loglik"] = (variants["fp32_loglik_evals_per_s"]

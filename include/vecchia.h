@@ -251,6 +251,15 @@ typedef struct {
  * a mismatch. */
 int32_t vecchia_plan_layout(int64_t* out, int32_t cap);
 size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
+/* Name of the kernel that size class q of a plan runs for a value call
+ * (with_grad = 0) or a value + gradient call in the given precision, for
+ * profiles and benchmark reports, e.g. "bv_wave_kernel<float,9,5>" (one-wave
+ * kernel, FP32, G = 9 tile rows, mode 5: gradient with the factor kept in
+ * registers; mode 1: through the tile buffer; "...,2>+...,3>": the split
+ * gradient, factorisation then adjoint).  Host only.  VECCHIA_EINVAL for a bad
+ * class index, VECCHIA_ENOMEM if cap bytes cannot hold the name. */
+int vecchia_plan_class_kernel(const vecchia_plan* plan, int32_t q, int32_t precision, int32_t with_grad,
+                              char* name, int32_t cap);
 /* Tile configuration of a size class (plan->bucket_cfg[q]) of an engine: tile
  * size R and tile-grid order G (joint capacity R*G; the matrix-core engine has
  * R = 16 and holds the bordered matrix, p + 1 <= 16 G).  VECCHIA_EINVAL for an

@@ -85,6 +85,7 @@ SIGNATURES = {
     "vecchia_condsim_workspace_size": (SZ, [I64]),
     "vecchia_condsim": (ctypes.c_int, [P, P, I64, P, I32, P, P, P, P, P, P, P, SZ, P]),
     "vecchia_plan_layout": (I32, [P, I32]),
+    "vecchia_plan_class_kernel": (ctypes.c_int, [P, I32, I32, I32, ctypes.c_char_p, I32]),
 }
 
 _lib = None

@@ -191,6 +191,13 @@ class Plan:
         L.check(L.lib().vecchia_plan_timing(ctypes.byref(self.c), ms, cnt, 1 if reset else 0), "vecchia_plan_timing")
         return [(float(ms[q]), int(cnt[q])) for q in range(nb + 1)]
 
+    def class_kernel(self, q: int, precision: str = "fp32", grad: bool = True) -> str:
+        """Name of the kernel size class q runs (vecchia_plan_class_kernel)."""
+        buf = ctypes.create_string_buffer(128)
+        L.check(L.lib().vecchia_plan_class_kernel(ctypes.byref(self.c), q, PRECISIONS[precision], 1 if grad else 0,
+                                                  buf, 128), "vecchia_plan_class_kernel")
+        return buf.value.decode()
+
     def flags(self) -> torch.Tensor:
         """Per (theta, block) flags of the last evaluation (device int32 view
         [max_theta, bc] into the plan workspace): 1 FP32 guard tripped, 2 not

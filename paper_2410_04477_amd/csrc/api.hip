@@ -2,6 +2,7 @@
 // launch orchestration.  Every numerical step runs in the HIP kernels.
 #include <math.h>
 #include <stddef.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <vector>
@@ -329,6 +330,39 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 // fits them (engine MFMA), else the four-wave kernels.  mode 0: value,
 // 1: value + gradient.  VECCHIA_EUNSUPPORTED when the four-wave adjoint's
 // right-hand sides do not fit the device LDS.
+// One-wave kernel mode that size class q runs for a value (with_grad = 0) or
+// value + gradient call: 0 value, 5 gradient with the factor in registers,
+// 1 gradient through the tile buffer, 23 the split gradient (mode 2 then 3);
+// -1 when the class does not run the one-wave kernels.
+static int class_wave_mode(const vecchia_plan* plan, int q, bool fp32, bool with_grad) {
+  const int g = plan->bucket_cfg[q] + 1;
+  if (plan->engine != kEngineMfma || plan->bucket_cfg[q] == kLargeCfg || !wave_fits(g, fp32)) return -1;
+  if (!with_grad) return 0;
+  if (wave_regadj(g, fp32, plan->bucket_lmax[q])) return 5;
+  return wave_split(g, fp32) ? 23 : 1;
+}
+
+extern "C" int vecchia_plan_class_kernel(const vecchia_plan* plan, int32_t q, int32_t precision, int32_t with_grad,
+                                         char* name, int32_t cap) {
+  if (!plan || q < 0 || q >= plan->nbuckets || !name || cap < 1) return VECCHIA_EINVAL;
+  const bool fp32 = precision != VECCHIA_FP64;
+  const char* t = fp32 ? "float" : "double";
+  const int g = plan->bucket_cfg[q] + 1;
+  const int mode = class_wave_mode(plan, q, fp32, with_grad != 0);
+  int n;
+  if (plan->bucket_cfg[q] == kLargeCfg)
+    n = snprintf(name, (size_t)cap, "bv_large_kernel<%s>", t);
+  else if (mode == 23)
+    n = snprintf(name, (size_t)cap, "bv_wave_kernel<%s,%d,2>+bv_wave_kernel<%s,%d,3>", t, g, t, g);
+  else if (mode >= 0)
+    n = snprintf(name, (size_t)cap, "bv_wave_kernel<%s,%d,%d>", t, g, mode);
+  else if (plan->engine == kEngineTiles)
+    n = snprintf(name, (size_t)cap, "bv_%s_kernel<%s,cfg%d>", with_grad ? "adj" : "fwd", t, plan->bucket_cfg[q]);
+  else
+    n = snprintf(name, (size_t)cap, "bv_mfma_kernel<%s,%d,%d>", t, g, with_grad ? 1 : 0);
+  return n >= 0 && n < cap ? VECCHIA_OK : VECCHIA_ENOMEM;
+}
+
 static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mode, AdjArgs a, const ThetaPack& thp,
                              int grid, hipStream_t s, void* tiles, size_t tile_bytes, hipStream_t s2 = nullptr,
                              hipEvent_t mark = nullptr) {
@@ -340,7 +374,7 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
       VCHECK_HIP(launch_wave(g, fp32, 0, a, thp, grid, s));
       return VECCHIA_OK;
     }
-    if (wave_regadj(g, fp32, plan->bucket_lmax[q])) {   // no tile buffer needed
+    if (class_wave_mode(plan, q, fp32, true) == 5) {   // no tile buffer needed
       VCHECK_HIP(launch_wave(g, fp32, 5, a, thp, grid, s));
       return VECCHIA_OK;
     }
