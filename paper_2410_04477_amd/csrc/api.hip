@@ -336,6 +336,9 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 // -1 when the class does not run the one-wave kernels.
 static int class_wave_mode(const vecchia_plan* plan, int q, bool fp32, bool with_grad) {
   const int g = plan->bucket_cfg[q] + 1;
+  // (the FP64 one-wave kernels above G = 9 spill part of their tiles, yet at
+  // n = 1e6 they run 84 evals/s of value + gradient against 55 for the
+  // four-wave kernels, whose tiles fit)
   if (plan->engine != kEngineMfma || plan->bucket_cfg[q] == kLargeCfg || !wave_fits(g, fp32)) return -1;
   if (!with_grad) return 0;
   if (wave_regadj(g, fp32, plan->bucket_lmax[q])) return 5;
@@ -369,12 +372,13 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
   const int g = plan->bucket_cfg[q] + 1;
   a.gen = 0;
   for (int t = 0; t < a.ntheta; ++t) a.gen |= thp.t[t].nu_code == 3;
-  if (plan->engine == kEngineMfma && wave_fits(g, fp32)) {
+  const int wmode = class_wave_mode(plan, q, fp32, mode != 0);
+  if (wmode >= 0) {
     if (mode == 0) {
       VCHECK_HIP(launch_wave(g, fp32, 0, a, thp, grid, s));
       return VECCHIA_OK;
     }
-    if (class_wave_mode(plan, q, fp32, true) == 5) {   // no tile buffer needed
+    if (wmode == 5) {   // no tile buffer needed
       VCHECK_HIP(launch_wave(g, fp32, 5, a, thp, grid, s));
       return VECCHIA_OK;
     }

@@ -82,7 +82,9 @@ bool wave_fits(int g, bool fp32);
 // gradient as two launches (factor + tiles, then the adjoint from the tiles)
 inline bool wave_split(int g, bool fp32) { return fp32 && g >= 10; }
 // gradient in one launch with the factor kept in the registers (no tile
-// buffer): classes up to G = 9 whose right-hand sides (l_max + 2) fit one pass
+// buffer): classes up to G = 9 whose right-hand sides (l_max + 2) fit one
+// pass (FP32 G = 10, 11 would run one wave per SIMD, slower than the split
+// gradient's two launches: 243 against 266 evals/s at n = 1e6)
 #ifndef BV_REGADJ_MAX_G32
 #define BV_REGADJ_MAX_G32 9
 #endif

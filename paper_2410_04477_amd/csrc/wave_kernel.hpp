@@ -443,10 +443,11 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   }
 
   constexpr int CH = wave_chunk(G);   // right-hand sides per pass
+  constexpr int NQ = (CH + 15) / 16;             // 16-column tiles of one pass
   constexpr int LDX = CH + 1;
   // with CH < 32 the second 16-column tile is partly outside a row: its reads
   // there are harmless (other columns of the MFMA results), its writes masked
-  const bool colok = CH == 32 || 16 + lr < CH;
+  auto colok = [&](int q) __attribute__((always_inline)) { return (q + 1) * 16 <= CH || q * 16 + lr < CH; };
   constexpr int GM = G > 1 ? G - 1 : 1;   // tile rows above a diagonal step, at most
   const int nr = l + 2;
   const int Ip = p >> 4, rp = p & 15;
@@ -557,9 +558,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     static_for_down<0, G>(BV_CI(K) {
       BV_CV(K);
       if (K >= Gp) return;
-      acc_t dq[2];
+      acc_t dq[NQ];
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
+      for (int q = 0; q < NQ; ++q) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) dq[q][r] = T(0);
         if (q < nq) {
@@ -571,21 +572,21 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         }
       }
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
-        if (q < nq && (q == 0 || colok)) {
+      for (int q = 0; q < NQ; ++q)
+        if (q < nq && colok(q)) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) X[(K * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = dq[q][r];
         }
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
+      for (int q = 0; q < NQ; ++q)
 #pragma unroll
         for (int r = 0; r < 4; ++r) dq[q][r] = -dq[q][r];
       // rows above: X_J -= L_KJ^T X_K
       static_for<0, K>(BV_CI(J) {
         BV_CV(J);
-        acc_t cj[2];
+        acc_t cj[NQ];
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
+        for (int q = 0; q < NQ; ++q)
           if (q < nq) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) cj[q][r] = X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr];
@@ -593,11 +594,11 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
-          for (int q = 0; q < 2; ++q)
+          for (int q = 0; q < NQ; ++q)
             if (q < nq) cj[q] = M::op(acc[tix(K, J)][sb], dq[q][sb], cj[q]);
 #pragma unroll
-        for (int q = 0; q < 2; ++q)
-          if (q < nq && (q == 0 || colok)) {
+        for (int q = 0; q < NQ; ++q)
+          if (q < nq && colok(q)) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = cj[q][r];
           }
@@ -712,7 +713,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       __syncthreads();
 #pragma unroll
       for (int q = 0; q < 2; ++q)
-        if (q < nq && (q == 0 || colok)) {
+        if (q < nq && colok(q)) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) X[(K * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = dq[q][r];
         }
@@ -747,7 +748,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
           if (J < K) {
 #pragma unroll
             for (int q = 0; q < 2; ++q)
-              if (q < nq && (q == 0 || colok)) {
+              if (q < nq && colok(q)) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = cj[J][q][r];
               }

@@ -7,6 +7,7 @@ that also performs a plain device copy of known size.  The copy's readings
 calibrate the counters: bytes = counter * (known copy bytes / copy reading).
 
     python -m paper_2410_04477_amd.profiling kernels <kernel_trace.csv> --title T --command C
+    python -m paper_2410_04477_amd.profiling counters <pass1.csv> [<pass2.csv> ...] --kernel REGEX
     python -m paper_2410_04477_amd.profiling traffic <fetch.csv> <write.csv> --kernel REGEX \
         --name NAME --copy-bytes B --sha S [--calls REGEX] --out profiles/hbm_traffic.json
 """
@@ -110,6 +111,67 @@ def counter_per_dispatch(pmc_csv: str, counter: str, kernel_regex: str, calls_re
     return (sum(vals) / len(vals) if vals else float("nan")), len(vals)
 
 
+def counter_summary(pmc_csvs, kernel_regex: str, simds: int = 1024):
+    """Per-kernel means over the dispatches matching ``kernel_regex`` of every
+    counter in the given ``rocprofv3 --pmc`` CSVs (one per pass), with the
+    derived figures: dispatch time, per-wave instruction and cycle counts
+    (SQ_*_CYCLES and SQ_ACTIVE_INST_* count quad-cycles), MFMA busy share
+    SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE / XCDs * SIMDs) and the MFMA
+    rate SQ_INSTS_VALU_MFMA_MOPS_* * 512 / dispatch time.  Only each kernel's
+    main dispatches count (at least half its longest dispatch)."""
+    pat = re.compile(kernel_regex)
+    per = defaultdict(lambda: defaultdict(list))   # kernel -> counter -> values per dispatch
+    dur = defaultdict(list)
+    for path in pmc_csvs:
+        header, rows = _rows(path)
+        iname, idisp = _col(header, "kernel_name"), _col(header, "dispatch_id", "correlation_id")
+        icn, icv = _col(header, "counter_name"), _col(header, "counter_value")
+        i0, i1 = _col(header, "start_timestamp"), _col(header, "end_timestamp")
+        acc = defaultdict(float)
+        seen = {}
+        for row in rows:
+            if not pat.search(row[iname]):
+                continue
+            k = row[iname].split("(")[0].replace("void ", "").replace("bv::", "")
+            acc[(k, row[idisp], row[icn])] += float(row[icv])
+            seen[(k, row[idisp])] = (int(row[i1]) - int(row[i0])) * 1e-9
+        # the main dispatches of each kernel: the FP32 guard's FP64 re-runs also
+        # launch it over an empty list (a few microseconds), which would skew means
+        longest = defaultdict(float)
+        for (k, d), t in seen.items():
+            longest[k] = max(longest[k], t)
+        main = {(k, d) for (k, d), t in seen.items() if t >= 0.5 * longest[k]}
+        for (k, d, c), v in acc.items():
+            if (k, d) in main:
+                per[k][c].append(v)
+        for (k, d) in main:
+            dur[k].append(seen[(k, d)])
+    out = {}
+    for k, cs in per.items():
+        m = {c: sum(v) / len(v) for c, v in cs.items()}
+        t = sorted(dur[k])[len(dur[k]) // 2]
+        waves = m.get("SQ_WAVES", float("nan"))
+        r = {"dispatches": len(dur[k]), "median_ms": t * 1e3, "waves": waves}
+        for c in ("SQ_INSTS_VALU", "SQ_INSTS_MFMA", "SQ_INSTS_LDS", "SQ_INSTS_SALU", "SQ_INSTS_VALU_TRANS_F32"):
+            if c in m:
+                r[c + "_per_wave"] = m[c] / waves
+        for c in ("SQ_WAVE_CYCLES", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+                  "SQ_WAIT_INST_LDS"):
+            if c in m:
+                r[c + "_cycles_per_wave"] = 4.0 * m[c] / waves
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in m:
+            r["SQ_VALU_MFMA_BUSY_CYCLES_per_wave"] = m["SQ_VALU_MFMA_BUSY_CYCLES"] / waves
+            if "GRBM_GUI_ACTIVE" in m:
+                r["mfma_busy_share"] = m["SQ_VALU_MFMA_BUSY_CYCLES"] / (m["GRBM_GUI_ACTIVE"] / 8.0 * simds)
+        mops = m.get("SQ_INSTS_VALU_MFMA_MOPS_F32", 0.0) + m.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0)
+        if mops:
+            r["mfma_tflops"] = mops * 512.0 / t / 1e12
+        if "SQ_LDS_BANK_CONFLICT" in m and "SQ_ACTIVE_INST_LDS" in m:
+            r["lds_bank_conflict_per_active_lds_cycle"] = m["SQ_LDS_BANK_CONFLICT"] / (4.0 * m["SQ_ACTIVE_INST_LDS"])
+        out[k] = r
+    return out
+
+
 COPY_REGEX = r"elementwise|copy|Copy"
 
 
@@ -151,6 +213,10 @@ def main(argv=None) -> int:
     k.add_argument("--span-min-dispatches", type=int, default=2)
     k.add_argument("--span-gap-us", type=float, default=0.0,
                    help="also join dispatches starting at most this long after a run's end")
+    c = sub.add_parser("counters")
+    c.add_argument("pmc_csv", nargs="+")
+    c.add_argument("--kernel", required=True, help="regex of the kernel names to summarise")
+    c.add_argument("--simds", type=int, default=1024)
     t = sub.add_parser("traffic")
     t.add_argument("fetch_csv")
     t.add_argument("write_csv")
@@ -173,6 +239,9 @@ def main(argv=None) -> int:
                                  f"{a.span_min_dispatches} overlapping dispatches{gap}): mean "
                                  f"{sum(sel) / len(sel) / 1e3:.1f} us, min {min(sel) / 1e3:.1f} us, "
                                  f"max {max(sel) / 1e3:.1f} us.\n")
+        return 0
+    if a.cmd == "counters":
+        print(json.dumps(counter_summary(a.pmc_csv, a.kernel, a.simds), indent=1, sort_keys=True))
         return 0
     res = traffic(a.fetch_csv, a.write_csv, a.kernel, a.copy_bytes, calls_regex=a.calls)
     try:
