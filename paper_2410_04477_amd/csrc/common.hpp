@@ -172,6 +172,9 @@ struct MaternCoef {
     r = e * (T(1) + x * (c1 + c2 * x));
     dr = x * inv_range * e * (g0 + x * (g1 + g2 * x));
   }
+  __device__ __forceinline__ T drange(T x, T inv_range) const {
+    return x * inv_range * expneg<T>(x) * (g0 + x * (g1 + g2 * x));
+  }
 };
 
 // The correlation a kernel generates: closed forms (GEN = false), or the
@@ -193,6 +196,11 @@ template <typename T> struct MaternF<T, true> {
     matern_general((double)x, t.bes, &rr, &g);
     r = T(rr);
     dr = T(g) * inv_range;
+  }
+  __device__ __forceinline__ T drange(T x, T inv_range) const {
+    double rr, g;
+    matern_general((double)x, t.bes, &rr, &g);
+    return T(g) * inv_range;
   }
 };
 

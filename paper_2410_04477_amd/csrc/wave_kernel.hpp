@@ -455,7 +455,11 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   T* X = work;   // X[row * LDX + col], one chunk of right-hand sides
 
   const T irange = T(th.inv_range);
-  double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  // d/d sigma2 needs no entry of dK: with d K_J / d sigma2 = (K_J - nugget I) / sigma2,
+  // <W, K_J> = ||w||^2 - ||w_N||^2 - l (the quadratic forms of y_J and y_N, and
+  // tr(X_R^T K_J X_R) = l) and tr W = 2 d l / d nugget, so that
+  // d l / d sigma2 = (sum_{k >= m} w_k^2 - l - nugget tr W) / (2 sigma2)
+  double g1 = 0.0, g2 = 0.0, qb = 0.0;
   // W = alpha alpha^T - b b^T - X_R X_R^T over the right-hand sides [cb, cb + nc)
   // held in X, contracted with dK regenerated entry by entry
   auto contract = [&](int cb, int nc) __attribute__((always_inline)) {
@@ -491,14 +495,11 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         if (J < I) cn = wtile(J + 1);
         const int j = J * 16 + lr;
         const T sj0 = su[j], sj1 = su[P + j], sj2 = su[2 * P + j];
-        T s0 = T(0), s1 = T(0), s2 = T(0);
+        T s1 = T(0), s2 = T(0);
         auto entry = [&](int r) __attribute__((always_inline)) {
           const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
           const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
-          T rho, drho;
-          mc.rho_drange(x, irange, rho, drho);
-          s0 += c[r] * rho;
-          s1 += c[r] * drho;
+          s1 += c[r] * mc.drange(x, irange);
         };
         if ((I + 1) * 16 <= p) {   // a tile inside the point rows (wave-uniform)
 #pragma unroll
@@ -514,7 +515,6 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
             if (M::row(lg, r) == lr && j < p) s2 += c[r];
         }
         const double wgt = I == J ? 1.0 : 2.0;
-        g0 += wgt * (double)s0;
         g1 += wgt * (double)s1;
         g2 += (double)s2;
       }
@@ -532,6 +532,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     for (int k = 0; k < NW; ++k) {
       const int j = ln + 64 * k;
       wreg[k] = j < p ? swk[j] : T(0);
+      if (j >= m && j < p) qb += (double)wreg[k] * (double)wreg[k];
     }
     __syncthreads();
     // right-hand sides [ w | [z; 0] | [0; I_l] ] (nr <= CH: one pass)
@@ -615,6 +616,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   for (int k = 0; k < NW; ++k) {
     const int j = ln + 64 * k;
     wreg[k] = j < p ? Lg[(Ip * (Ip + 1) / 2 + (j >> 4)) * 256 + M::at(rp, j & 15)] : T(0);
+    if (j >= m && j < p) qb += (double)wreg[k] * (double)wreg[k];
   }
 
   // ---- inverses of the diagonal 16 x 16 blocks of L ---------------------------
@@ -762,7 +764,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   }   // MODE != 5
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
-    g0 += __shfl_down(g0, off, 64);
+    qb += __shfl_down(qb, off, 64);
     g1 += __shfl_down(g1, off, 64);
     g2 += __shfl_down(g2, off, 64);
   }
@@ -772,7 +774,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       a.partial[o] = bad ? __builtin_nan("") : -0.5 * (acc_ll + (double)l * kLog2Pi);
       a.flag[o] = flag | a.flag_or;
     }
-    a.gpart[3 * o + 0] = bad ? __builtin_nan("") : 0.5 * g0;
+    a.gpart[3 * o + 0] = bad ? __builtin_nan("") : 0.5 * (qb - (double)l - th.nugget * g2) / th.sigma2;
     a.gpart[3 * o + 1] = bad ? __builtin_nan("") : 0.5 * th.sigma2 * g1;
     a.gpart[3 * o + 2] = bad ? __builtin_nan("") : 0.5 * g2;
   }
