@@ -246,8 +246,17 @@ def main() -> int:
             model.loglik_grad([th_g[i % len(th_g)]], "fp32")
         torch.cuda.synchronize()
         variants["fp32_loglik_grad_nu1.0_bessel_evals_per_s"] = k2 / (time.perf_counter() - t0)
-        # d l / d nu (two FP64 Bessel-form log-likelihoods per theta)
-        log("timing d l / d nu at nu = 1.0")
+        # value and all four derivatives (sigma2, range, nugget, nu) from the adjoint
+        log("timing fp32 loglik + gradient incl. d / d nu at nu = 1.0 (adjoint)")
+        model.loglik_grad_nu(th_g[:1], "fp32")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(k2):
+            model.loglik_grad_nu([th_g[i % len(th_g)]], "fp32")
+        torch.cuda.synchronize()
+        variants["fp32_loglik_grad_with_nu_nu1.0_evals_per_s"] = k2 / (time.perf_counter() - t0)
+        # d l / d nu alone as a central difference (two FP64 Bessel-form log-likelihoods per theta)
+        log("timing d l / d nu at nu = 1.0 (central difference)")
         model.loglik_dnu(th_g[:1])
         torch.cuda.synchronize()
         t0 = time.perf_counter()

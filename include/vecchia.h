@@ -358,6 +358,26 @@ int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const
                         double* loglik, double* grad, int32_t* counters, double* partial, double* gpartial,
                         void* stream);
 
+/* -------------------------------------------------------- loglik_grad_nu --
+ * Log-likelihood and its gradient w.r.t. (sigma2, range, nugget) and the
+ * Matern smoothness nu (eq. (maternkernel)), as estimated in Section 3: the
+ * adjoint of vecchia_loglik_grad with one more contraction,
+ *   d l_i / d nu = 1/2 <W, sigma2 d rho / d nu>,
+ * where d rho / d nu = 2^(1-nu)/Gamma(nu) x^nu [K_nu (log x - log 2 -
+ * psi(nu)) + d K_nu / d nu], and d K_nu / d nu is the trapezoidal rule on
+ * int_0^inf t exp(-x cosh t) sinh(nu t) dt (at the reduced order, raised by
+ * the differentiated recurrence).  Every nu in [0.05, 10], including the
+ * half-integers, goes through the Bessel-form kernels, so the plan must use
+ * engine VECCHIA_ENGINE_MFMA with no block above VECCHIA_MAX_JOINT (else
+ * VECCHIA_EUNSUPPORTED).  Arguments as vecchia_loglik_grad, plus
+ *   dnu          out, ntheta doubles: d l / d nu
+ *   gpartial_nu  out or NULL, ntheta*bc doubles: per-block d l_i / d nu */
+int vecchia_loglik_grad_nu(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                           const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                           const vecchia_theta* theta, int32_t ntheta, int32_t precision,
+                           double* loglik, double* grad, double* dnu, int32_t* counters, double* partial,
+                           double* gpartial, double* gpartial_nu, void* stream);
+
 /* ------------------------------------------------------------ loglik_dnu --
  * Derivative of the log-likelihood w.r.t. the Matern smoothness nu (eq.
  * (maternkernel)), for estimating nu together with the other parameters as
@@ -367,7 +387,7 @@ int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const
  * no block above the one-wave limit.  Truncation error is of order
  * (rel_step nu)^2 |d3 l / d nu3| / 6, rounding error of order
  * 1e-16 |l| / (rel_step nu); rel_step = 1e-4 balances them for FP64.
- * There is no adjoint for nu (d K_nu / d nu has no closed form).
+ * (vecchia_loglik_grad_nu gives the same derivative from the adjoint.)
  *   theta, ntheta   host, as vecchia_loglik (precision is always FP64)
  *   rel_step        relative step, in (0, 0.1]
  *   dnu             out, device, ntheta doubles

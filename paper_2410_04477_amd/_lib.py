@@ -64,6 +64,7 @@ SIGNATURES = {
     "vecchia_permute": (ctypes.c_int, [P, I64, I32, P, P, P]),
     "vecchia_loglik_grad": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P, P, P]),
     "vecchia_loglik_dnu": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, ctypes.c_double, P, P, P]),
+    "vecchia_loglik_grad_nu": (ctypes.c_int, [P, P, P, I32, P, P, P, P, I32, I32, P, P, P, P, P, P, P, P]),
     "vecchia_simulate_workspace_size": (SZ, [I64, I64, I32]),
     "vecchia_simulate": (ctypes.c_int, [P, I64, I32, P, P, P, I32, P, P, P, SZ, P]),
     "vecchia_variogram_workspace_size": (SZ, [I32, I32, I32]),

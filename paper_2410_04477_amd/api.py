@@ -276,6 +276,34 @@ def loglik_grad(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_i
     return out, grad, cnt, part, gpart
 
 
+def loglik_grad_nu(plan: Plan, locs_perm: torch.Tensor, y_perm: torch.Tensor, nbr_idx: torch.Tensor,
+                   thetas: Iterable, precision: str = "fp64", want_partial: bool = False):
+    """Log-likelihood and its gradient w.r.t. (sigma2, range, nugget, nu) for
+    each theta, all from the adjoint (vecchia_loglik_grad_nu).  Returns
+    (loglik[nt], grad[nt, 4], counters[nt, 2], partial[nt, bc] | None,
+    gpartial[nt, bc, 4] | None) as device tensors."""
+    _dev_check(locs_perm, y_perm, nbr_idx)
+    th = [make_theta(t) for t in thetas]
+    nt = len(th)
+    arr = (L.Theta * nt)(*th)
+    dev = locs_perm.device
+    out = torch.empty(nt, dtype=torch.float64, device=dev)
+    grad = torch.empty((nt, 3), dtype=torch.float64, device=dev)
+    dnu = torch.empty(nt, dtype=torch.float64, device=dev)
+    cnt = torch.empty((nt, 2), dtype=torch.int32, device=dev)
+    part = torch.empty((nt, plan.bc), dtype=torch.float64, device=dev) if want_partial else None
+    gpart = torch.empty((nt, plan.bc, 3), dtype=torch.float64, device=dev) if want_partial else None
+    gnu = torch.empty((nt, plan.bc), dtype=torch.float64, device=dev) if want_partial else None
+    d = 1 if locs_perm.dim() == 1 else locs_perm.shape[1]
+    L.check(L.lib().vecchia_loglik_grad_nu(ctypes.byref(plan.c), _p(locs_perm), _p(y_perm), d, _p(plan.block_ptr),
+                                           _p(plan.nbr_ptr), _p(nbr_idx), arr, nt, PRECISIONS[precision], _p(out),
+                                           _p(grad), _p(dnu), _p(cnt), _p(part), _p(gpart), _p(gnu), _stream(dev)),
+            "vecchia_loglik_grad_nu")
+    g4 = torch.cat([grad, dnu[:, None]], 1)
+    gp4 = torch.cat([gpart, gnu[:, :, None]], 2) if want_partial else None
+    return out, g4, cnt, part, gp4
+
+
 def simulate(locs_ord: torch.Tensor, nbr_ptr: torch.Tensor, nbr_idx: torch.Tensor, theta,
              z: torch.Tensor) -> torch.Tensor:
     """Sequential Vecchia draw in the given point order (see vecchia_simulate).

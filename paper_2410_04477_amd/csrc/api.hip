@@ -66,10 +66,27 @@ PlanLayout plan_layout(int64_t bc, int32_t max_theta) {
   L.list = o;    o = align256(o + sizeof(int) * nb * nt);
   L.count = o;   o = align256(o + sizeof(int) * 64);
   L.chunk = o;   o = align256(o + sizeof(double) * 64);
-  L.grad = o;    o = align256(o + sizeof(double) * nb * nt * 3);
+  L.grad = o;    o = align256(o + sizeof(double) * nb * nt * 4);   // 3 per block, then d/d nu per block
   L.scratch = o; o = align256(o + sizeof(int) * (nb + 256) + sizeof(unsigned long long) * 8);
   L.total = o;
   return L;
+}
+
+// Digamma psi(x) for x > 0: the recurrence psi(x) = psi(x + 1) - 1/x up to
+// x >= 8, then the asymptotic series psi(x) ~ log x - 1/(2x) - sum_k
+// B_2k / (2k x^2k) (Abramowitz and Stegun 6.3.18) to the x^-14 term, whose
+// first omitted term is below 1e-17 there.
+static double digamma(double x) {
+  double acc = 0.0;
+  while (x < 8.0) {
+    acc -= 1.0 / x;
+    x += 1.0;
+  }
+  const double r = 1.0 / (x * x);
+  // B_2k / (2k): 1/12, -1/120, 1/252, -1/240, 1/132, -691/32760, 1/12
+  const double series =
+      r * (1.0 / 12 - r * (1.0 / 120 - r * (1.0 / 252 - r * (1.0 / 240 - r * (1.0 / 132 - r * (691.0 / 32760 - r / 12))))));
+  return acc + log(x) - 0.5 / x - series;
 }
 
 // Orders of the Bessel form: nu in [kNuMin, kNuMax] (outside the closed forms).
@@ -101,6 +118,7 @@ int theta_status(const vecchia_theta& t, int d, ThetaDev& o) {
     b.gam1 = fabs(mu) < 1e-3 ? -(0.5772156649015329 - 0.0420026350340952 * mu * mu) : (rm - rp) / (2.0 * mu);
     b.mu_pi_csc = fabs(mu) < 1e-14 ? 1.0 : M_PI * mu / sin(M_PI * mu);
     b.lognorm = (1.0 - t.nu) * log(2.0) - lgamma(t.nu);
+    b.dlognorm = -log(2.0) - digamma(t.nu);
   }
   o.sigma2 = t.sigma2;
   o.nugget = t.nugget;
@@ -370,7 +388,7 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
                              int grid, hipStream_t s, void* tiles, size_t tile_bytes, hipStream_t s2 = nullptr,
                              hipEvent_t mark = nullptr) {
   const int g = plan->bucket_cfg[q] + 1;
-  a.gen = 0;
+  a.gen = a.gnu != nullptr;   // d / d nu needs the Bessel-form kernels whatever nu is
   for (int t = 0; t < a.ntheta; ++t) a.gen |= thp.t[t].nu_code == 3;
   const int wmode = class_wave_mode(plan, q, fp32, mode != 0);
   if (wmode >= 0) {
@@ -743,15 +761,18 @@ extern "C" int vecchia_loglik(const vecchia_plan* plan, const double* locs_perm,
 
 // ----------------------------------------------------------- loglik_grad --
 
-extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const double* y_perm,
-                                   int32_t d, const int32_t* block_ptr, const int32_t* nbr_ptr,
-                                   const int32_t* nbr_idx, const vecchia_theta* theta, int32_t ntheta,
-                                   int32_t precision, double* loglik, double* grad, int32_t* counters,
-                                   double* partial, double* gpartial, void* stream) {
+// Value and gradient; with dnu (and optionally gpartial_nu) the derivative in
+// nu as well, through the Bessel-form kernels.
+static int loglik_grad_run(const vecchia_plan* plan, const double* locs_perm, const double* y_perm, int32_t d,
+                           const int32_t* block_ptr, const int32_t* nbr_ptr, const int32_t* nbr_idx,
+                           const vecchia_theta* theta, int32_t ntheta, int32_t precision, double* loglik,
+                           double* grad, double* dnu, int32_t* counters, double* partial, double* gpartial,
+                           double* gpartial_nu, void* stream) {
   int st = check_common(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision);
   if (st) return st;
   if (!loglik || !grad) return VECCHIA_EINVAL;
   if (plan->nlarge > 0) return VECCHIA_EUNSUPPORTED;  // gradient above the register capacity
+  if (dnu && plan->engine != kEngineMfma) return VECCHIA_EUNSUPPORTED;   // Bessel form: one-wave kernels only
   if (plan->aux_ws_bytes > 0 && !plan->aux_ws) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const int bc = (int)plan->bc;
@@ -760,6 +781,7 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
   const int* sched = at<int>(ws, plan->off_sched);
   double* part = at<double>(ws, plan->off_partial);
   double* gpart = at<double>(ws, plan->off_grad);
+  double* gnu = dnu ? gpart + (size_t)bc * plan->max_theta * 3 : nullptr;
   int* flag = at<int>(ws, plan->off_flag);
   int* list = at<int>(ws, plan->off_list);
   int* count = at<int>(ws, plan->off_count);
@@ -783,6 +805,7 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
     a.ldx = 0;   // set per size class
     a.partial = part;
     a.gpart = gpart;
+    a.gnu = gnu;
     a.flag = flag;
     // the one-wave adjoint's tile buffer is split among the size classes so
     // that they can run concurrently; if it is too small they run in turn
@@ -856,14 +879,38 @@ extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_
     VCHECK_HIP(launch_reduce_partials(part, flag, bc, nt, fp32 ? 0 : 1, loglik + t0,
                                       counters ? counters + 2 * t0 : nullptr, s));
     VCHECK_HIP(launch_reduce_vec(gpart, bc, 3, nt, grad + 3 * t0, s));
+    if (gnu) VCHECK_HIP(launch_reduce_vec(gnu, bc, 1, nt, dnu + t0, s));
     if (partial)
       VCHECK_HIP(hipMemcpyAsync(partial + (size_t)t0 * bc, part, sizeof(double) * (size_t)nt * bc,
                                 hipMemcpyDeviceToDevice, s));
     if (gpartial)
       VCHECK_HIP(hipMemcpyAsync(gpartial + (size_t)t0 * bc * 3, gpart, sizeof(double) * (size_t)nt * bc * 3,
                                 hipMemcpyDeviceToDevice, s));
+    if (gnu && gpartial_nu)
+      VCHECK_HIP(hipMemcpyAsync(gpartial_nu + (size_t)t0 * bc, gnu, sizeof(double) * (size_t)nt * bc,
+                                hipMemcpyDeviceToDevice, s));
   }
   return VECCHIA_OK;
+}
+
+extern "C" int vecchia_loglik_grad(const vecchia_plan* plan, const double* locs_perm, const double* y_perm,
+                                   int32_t d, const int32_t* block_ptr, const int32_t* nbr_ptr,
+                                   const int32_t* nbr_idx, const vecchia_theta* theta, int32_t ntheta,
+                                   int32_t precision, double* loglik, double* grad, int32_t* counters,
+                                   double* partial, double* gpartial, void* stream) {
+  return loglik_grad_run(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision, loglik,
+                         grad, nullptr, counters, partial, gpartial, nullptr, stream);
+}
+
+extern "C" int vecchia_loglik_grad_nu(const vecchia_plan* plan, const double* locs_perm, const double* y_perm,
+                                      int32_t d, const int32_t* block_ptr, const int32_t* nbr_ptr,
+                                      const int32_t* nbr_idx, const vecchia_theta* theta, int32_t ntheta,
+                                      int32_t precision, double* loglik, double* grad, double* dnu,
+                                      int32_t* counters, double* partial, double* gpartial, double* gpartial_nu,
+                                      void* stream) {
+  if (!dnu) return VECCHIA_EINVAL;
+  return loglik_grad_run(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision, loglik,
+                         grad, dnu, counters, partial, gpartial, gpartial_nu, stream);
 }
 
 // ------------------------------------------------------------- predict ----

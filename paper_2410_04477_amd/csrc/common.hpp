@@ -14,10 +14,10 @@ constexpr double kLog2Pi = 1.83787706640934548356065947281123527;
 // Order-only constants of the Bessel form (host-computed per theta): the
 // order nu = n + mu with |mu| <= 1/2; Gamma(1 + mu), Gamma(1 - mu); Temme's
 // Gamma1(mu) = (1/Gamma(1 - mu) - 1/Gamma(1 + mu)) / (2 mu) and Gamma2(mu) =
-// (1/Gamma(1 - mu) + 1/Gamma(1 + mu)) / 2; mu pi / sin(mu pi); and
-// log(2^(1 - nu) / Gamma(nu)).
+// (1/Gamma(1 - mu) + 1/Gamma(1 + mu)) / 2; mu pi / sin(mu pi);
+// log(2^(1 - nu) / Gamma(nu)) and its derivative in nu, -log 2 - psi(nu).
 struct BesselOrder {
-  double mu, gplus, gminus, gam1, gam2, mu_pi_csc, lognorm;
+  double mu, gplus, gminus, gam1, gam2, mu_pi_csc, lognorm, dlognorm;
   int n;
 };
 
@@ -136,6 +136,75 @@ __device__ __noinline__ inline void matern_general(double x, const BesselOrder& 
   *g = exp(o.lognorm + (nu + 1.0) * logx) * k_lo;
 }
 
+// rho and g as matern_general, and d rho / d nu.  K_mu, K_(mu+1) and their
+// derivatives in the order come from the trapezoidal rule on
+//   K_v(x) = int_0^inf exp(-x cosh t) cosh(v t) dt,
+//   d K_v / d v = int_0^inf t exp(-x cosh t) sinh(v t) dt
+// for every x > 0 (the same nodes serve all four; the step as in
+// bessel_k_pair_quad, nodes until the integrands fall below 1e-18 of the sums
+// and t > 1, at most 320: about 110 at x = 1e-4, fewer as x grows).  The
+// order is raised by the recurrence K_(v+1) = K_(v-1) + (2 v / x) K_v and its
+// derivative D_(v+1) = D_(v-1) + (2 v / x) D_v + (2 / x) K_v (mu moves with
+// nu).  Then d rho / d nu = 2^(1-nu)/Gamma(nu) x^nu [K_nu (log x - log 2 -
+// psi(nu)) + D_nu].
+__device__ __noinline__ inline void matern_general_dnu(double x, const BesselOrder& o, double* rho, double* g,
+                                                       double* drho_dnu) {
+  if (!(x > 0.0)) {
+    *rho = 1.0;
+    *g = 0.0;
+    *drho_dnu = 0.0;
+    return;
+  }
+  const double h = fmin(0.125, 0.7 * rsqrt(x));
+  const double a = exp(o.mu * h), ai = 1.0 / a, b = exp(h), bi = 1.0 / b;
+  double emu = 1.0, emui = 1.0, et = 1.0, eti = 1.0;
+  const double w0 = exp(-x);
+  double k0 = 0.5 * w0, k1 = 0.5 * w0, d0 = 0.0, d1 = 0.0;   // t = 0: weight 1/2, sinh(0) = 0
+  for (int k = 1; k < 320; ++k) {
+    emu *= a;
+    emui *= ai;
+    et *= b;
+    eti *= bi;
+    const double t = k * h;
+    const double w = exp(-0.5 * x * (et + eti));
+    const double c1 = 0.5 * (emu * et + emui * eti), s1 = 0.5 * (emu * et - emui * eti);
+    k0 += w * 0.5 * (emu + emui);
+    k1 += w * c1;
+    d0 += w * t * 0.5 * (emu - emui);
+    d1 += w * t * s1;
+    if (t > 1.0 && w * t * c1 < 1e-18 * k1) break;
+  }
+  k0 *= h;
+  k1 *= h;
+  d0 *= h;
+  d1 *= h;
+  double klo, khi, dhi;   // K_(nu-1), K_nu, d K_nu / d nu
+  if (o.n == 0) {
+    klo = k1 - (2.0 * o.mu / x) * k0;
+    khi = k0;
+    dhi = d0;
+  } else {
+    klo = k0;
+    khi = k1;
+    double dlo = d0;
+    dhi = d1;
+    for (int v = 1; v < o.n; ++v) {
+      const double vv = o.mu + v;
+      const double kn = klo + (2.0 * vv / x) * khi;
+      const double dn = dlo + (2.0 * vv / x) * dhi + (2.0 / x) * khi;
+      klo = khi;
+      khi = kn;
+      dlo = dhi;
+      dhi = dn;
+    }
+  }
+  const double nu = o.mu + o.n, logx = log(x);
+  const double c = exp(o.lognorm + nu * logx);
+  *rho = c * khi;
+  *g = c * x * klo;
+  *drho_dnu = c * (khi * (logx + o.dlognorm) + dhi);
+}
+
 template <typename T> __device__ __forceinline__ T expneg(T x);
 template <> __device__ __forceinline__ double expneg<double>(double x) { return exp(-x); }
 template <> __device__ __forceinline__ float expneg<float>(float x) { return __expf(-x); }
@@ -201,6 +270,13 @@ template <typename T> struct MaternF<T, true> {
     double rr, g;
     matern_general((double)x, t.bes, &rr, &g);
     return T(g) * inv_range;
+  }
+  // d rho / d range and d rho / d nu (the derivative in nu by quadrature)
+  __device__ __forceinline__ void drange_dnu(T x, T inv_range, T& dr, T& dn) const {
+    double rr, g, d;
+    matern_general_dnu((double)x, t.bes, &rr, &g, &d);
+    dr = T(g) * inv_range;
+    dn = T(d);
   }
 };
 

@@ -58,6 +58,7 @@ struct AdjArgs {
   double* out_cov;       // [block][ldc][ldc]: conditional covariance, or null
   int ldc;
   int gen;               // some theta of the launch has nu outside {1/2, 3/2, 5/2} (Bessel form)
+  double* gnu;           // Bessel-form gradient launches: d l_i / d nu [theta * bc + block], or null
 };
 
 hipError_t launch_adjoint(int cfg, bool fp32, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s);

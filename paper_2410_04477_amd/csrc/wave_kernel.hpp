@@ -459,7 +459,8 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   // <W, K_J> = ||w||^2 - ||w_N||^2 - l (the quadratic forms of y_J and y_N, and
   // tr(X_R^T K_J X_R) = l) and tr W = 2 d l / d nugget, so that
   // d l / d sigma2 = (sum_{k >= m} w_k^2 - l - nugget tr W) / (2 sigma2)
-  double g1 = 0.0, g2 = 0.0, qb = 0.0;
+  double g1 = 0.0, g2 = 0.0, qb = 0.0, g3 = 0.0;   // g3: <W, d rho / d nu> (Bessel form, on request)
+  const bool want_nu = GEN && a.gnu != nullptr;
   // W = alpha alpha^T - b b^T - X_R X_R^T over the right-hand sides [cb, cb + nc)
   // held in X, contracted with dK regenerated entry by entry
   auto contract = [&](int cb, int nc) __attribute__((always_inline)) {
@@ -495,11 +496,22 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         if (J < I) cn = wtile(J + 1);
         const int j = J * 16 + lr;
         const T sj0 = su[j], sj1 = su[P + j], sj2 = su[2 * P + j];
-        T s1 = T(0), s2 = T(0);
+        T s1 = T(0), s2 = T(0), s3 = T(0);
         auto entry = [&](int r) __attribute__((always_inline)) {
           const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
           const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
-          s1 += c[r] * mc.drange(x, irange);
+          if constexpr (GEN) {
+            if (want_nu) {
+              T dr, dn;
+              mc.drange_dnu(x, irange, dr, dn);
+              s1 += c[r] * dr;
+              s3 += c[r] * dn;
+            } else {
+              s1 += c[r] * mc.drange(x, irange);
+            }
+          } else {
+            s1 += c[r] * mc.drange(x, irange);
+          }
         };
         if ((I + 1) * 16 <= p) {   // a tile inside the point rows (wave-uniform)
 #pragma unroll
@@ -517,6 +529,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         const double wgt = I == J ? 1.0 : 2.0;
         g1 += wgt * (double)s1;
         g2 += (double)s2;
+        if (GEN) g3 += wgt * (double)s3;
       }
     }
   };
@@ -765,6 +778,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
     qb += __shfl_down(qb, off, 64);
+    if (GEN) g3 += __shfl_down(g3, off, 64);
     g1 += __shfl_down(g1, off, 64);
     g2 += __shfl_down(g2, off, 64);
   }
@@ -777,6 +791,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     a.gpart[3 * o + 0] = bad ? __builtin_nan("") : 0.5 * (qb - (double)l - th.nugget * g2) / th.sigma2;
     a.gpart[3 * o + 1] = bad ? __builtin_nan("") : 0.5 * th.sigma2 * g1;
     a.gpart[3 * o + 2] = bad ? __builtin_nan("") : 0.5 * g2;
+    if (want_nu) a.gnu[o] = bad ? __builtin_nan("") : 0.5 * th.sigma2 * g3;
   }
 }
 

@@ -98,6 +98,10 @@ class BlockVecchia:
                                want_partial)
 
 
+    def loglik_grad_nu(self, thetas, precision: str = "fp64", want_partial: bool = False):
+        return api.loglik_grad_nu(self.plan, self.locs_perm, self.y_perm, self.nbr_idx, thetas, precision,
+                                  want_partial)
+
     def loglik_dnu(self, thetas, rel_step: float = 1e-4):
         return api.loglik_dnu(self.plan, self.locs_perm, self.y_perm, self.nbr_idx, thetas, rel_step)
 
@@ -126,17 +130,15 @@ def vecchia_loglik(params: torch.Tensor, model: BlockVecchia, precision: str = "
 
 
 class VecchiaLogLikNu(torch.autograd.Function):
-    """l(sigma2, range, nugget, nu): the adjoint gradient for the first three
-    parameters (in the requested precision) and d l / d nu from the library's
-    FP64 central difference in nu."""
+    """l(sigma2, range, nugget, nu) with all four derivatives from the
+    library's adjoint (d l / d nu through d K_nu / d nu in the contraction)."""
 
     @staticmethod
     def forward(ctx, params: torch.Tensor, model: BlockVecchia, precision: str = "fp64"):
         p = params.detach().to(torch.float64).cpu().tolist()
         th = model.theta(*p)
-        ll, g, cnt, _, _ = model.loglik_grad([th], precision)
-        dnu = model.loglik_dnu([th])
-        ctx.save_for_backward(torch.cat([g[0], dnu]).to(params.device, params.dtype))
+        ll, g, cnt, _, _ = model.loglik_grad_nu([th], precision)
+        ctx.save_for_backward(g[0].to(params.device, params.dtype))
         ctx.counters = cnt
         return ll[0].to(params.device, params.dtype)
 
