@@ -199,12 +199,14 @@ typedef enum { VECCHIA_ENGINE_MFMA = 0, VECCHIA_ENGINE_TILES = 1, VECCHIA_ENGINE
  *   max_theta    largest ntheta that later calls will pass
  *   workspace    >= vecchia_plan_workspace_size(bc, max_theta) bytes
  * Blocks with m_i + l_i above VECCHIA_MAX_JOINT (up to 16383) form a size class
- * of their own: each is generated into a global workspace and factored
+ * of their own: each is generated into a global workspace slot and factored
  * left-looking in 16-column panels with MFMA panel updates;
- * vecchia_loglik_grad returns VECCHIA_EUNSUPPORTED for them.
+ * vecchia_loglik_grad and vecchia_loglik_grad_nu return VECCHIA_EUNSUPPORTED
+ * for plans that contain such blocks (their adjoint kernel is built but
+ * switched off).
  * Auxiliary workspace: plan->aux_ws_bytes bytes (0 when not needed), attached
  * with vecchia_plan_attach_aux before the first evaluation, holds the large
- * blocks' matrices and, for engine MFMA, the per-block factor tiles of the
+ * blocks' slots and, after them, for engine MFMA, the per-block factor tiles of the
  * size classes whose adjoint goes through the tile buffer (at most 4 GiB;
  * the adjoint launches in chunks that fit it).  A smaller
  * buffer is accepted down to the size that holds every large-block slot and

@@ -252,11 +252,10 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
     plan->bucket_lmax[nb] = hlmax[kLargeCfg];
     ++nb;
     acc += hcounts[kLargeCfg];
-    const int64_t P = 16 * (int64_t)((hmax[0] + 1 + 15) / 16);
     const int64_t work = plan->nlarge * (int64_t)max_theta;
     plan->large_slots = (int32_t)(work < 256 ? work : 256);
-    plan->large_slot_elems = P * P;
-    plan->aux_ws_bytes = (size_t)plan->large_slots * (size_t)(P * P) * sizeof(double);
+    plan->large_slot_elems = (int64_t)large_slot_elems(hmax[0], hlmax[kLargeCfg]);
+    plan->aux_ws_bytes = (size_t)plan->large_slots * (size_t)plan->large_slot_elems * sizeof(double);
   }
   if (engine == kEngineMfma && !predict) {
     // adjoint factor tiles, FP64, of every work item of the classes whose
@@ -267,7 +266,7 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
       if (hcounts[c] > 0 && wave_fits(c + 1, false) && !wave_regadj(c + 1, false, hlmax[c]))
         need += (size_t)hcounts[c] * (size_t)max_theta * wave_tile_bytes(c + 1, false);
     if (need > kAdjTileCap) need = kAdjTileCap;
-    if (need > plan->aux_ws_bytes) plan->aux_ws_bytes = need;
+    plan->aux_ws_bytes += need;   // the tile buffer follows the large-block slots
   }
   plan->bucket_off[nb] = acc;
   plan->nbuckets = nb;
@@ -570,19 +569,25 @@ extern "C" int vecchia_plan_timing(vecchia_plan* plan, double* ms, int64_t* laun
   return VECCHIA_OK;
 }
 
+// Bytes of the large-block slots at the start of the auxiliary workspace (the
+// one-wave adjoint's tile buffer follows them).
+static size_t large_bytes(const vecchia_plan* plan) {
+  return plan->nlarge > 0 ? (size_t)plan->large_slots * (size_t)plan->large_slot_elems * sizeof(double) : 0;
+}
+
 // Smallest auxiliary workspace a plan can run with: every large-block slot,
 // and one work item's FP64 factor tiles of the largest one-wave class (the
 // adjoint then runs one item per launch).
 static size_t aux_min_bytes(const vecchia_plan* plan) {
-  size_t need = plan->nlarge > 0 ? (size_t)plan->large_slots * (size_t)plan->large_slot_elems * sizeof(double) : 0;
+  size_t item = 0;
   if (plan->engine == kEngineMfma && plan->kind == 0)
     for (int q = 0; q < plan->nbuckets; ++q) {
       const int g = plan->bucket_cfg[q] + 1;
       if (plan->bucket_cfg[q] != kLargeCfg && wave_fits(g, false) && !wave_regadj(g, false, plan->bucket_lmax[q]) &&
-          wave_tile_bytes(g, false) > need)
-        need = wave_tile_bytes(g, false);
+          wave_tile_bytes(g, false) > item)
+        item = wave_tile_bytes(g, false);
     }
-  return need;
+  return large_bytes(plan) + item;
 }
 
 extern "C" int vecchia_plan_attach_aux(vecchia_plan* plan, void* aux_workspace, size_t bytes) {
@@ -617,6 +622,32 @@ static LargeArgs as_large(const FwdArgs& f, const vecchia_plan* plan) {
   a.slot_elems = plan->large_slot_elems;
   a.partial = f.partial;
   a.flag = f.flag;
+  a.gpart = nullptr;
+  return a;
+}
+
+// Large-block arguments of a gradient launch.
+static LargeArgs as_large(const AdjArgs& f, const vecchia_plan* plan) {
+  FwdArgs w;
+  memset(&w, 0, sizeof(w));
+  w.locs = f.locs;
+  w.y = f.y;
+  w.block_ptr = f.block_ptr;
+  w.nbr_ptr = f.nbr_ptr;
+  w.nbr_idx = f.nbr_idx;
+  w.sched = f.sched;
+  w.list = f.list;
+  w.list_count = f.list_count;
+  w.nsched = f.nsched;
+  w.ntheta = f.ntheta;
+  w.bc = f.bc;
+  w.d = f.d;
+  w.fp32_guard = f.fp32_guard;
+  w.flag_or = f.flag_or;
+  w.partial = f.partial;
+  w.flag = f.flag;
+  LargeArgs a = as_large(w, plan);
+  a.gpart = f.gpart;
   return a;
 }
 
@@ -699,7 +730,7 @@ int bv::loglik_run(const vecchia_plan* plan, const double* locs_perm, const doub
       VCHECK_HIP(time_begin(plan, q, sq, tr));
       if (plan->bucket_cfg[q] == kLargeCfg) {
         const int g = ns * nt < plan->large_slots ? ns * nt : plan->large_slots;
-        VCHECK_HIP(launch_large(fp32, as_large(a, plan), thp, g, sq));
+        VCHECK_HIP(launch_large(fp32, false, as_large(a, plan), thp, g, sq));
       } else {
         if (plan->engine == kEngineTiles)
           VCHECK_HIP(launch_forward(plan->bucket_cfg[q], fp32, a, thp, ns * nt, sq));
@@ -727,7 +758,8 @@ int bv::loglik_run(const vecchia_plan* plan, const double* locs_perm, const doub
         r.list_count = count + q;
         const int cap = ns * nt;
         if (plan->bucket_cfg[q] == kLargeCfg)
-          VCHECK_HIP(launch_large(false, as_large(r, plan), thp, cap < plan->large_slots ? cap : plan->large_slots, s));
+          VCHECK_HIP(launch_large(false, false, as_large(r, plan), thp, cap < plan->large_slots ? cap : plan->large_slots,
+                                  s));
         else if (plan->engine == kEngineTiles)
           VCHECK_HIP(launch_forward(plan->bucket_cfg[q], false, r, thp, cap < 256 ? cap : 256, s));
         else
@@ -771,8 +803,12 @@ static int loglik_grad_run(const vecchia_plan* plan, const double* locs_perm, co
   int st = check_common(plan, locs_perm, y_perm, d, block_ptr, nbr_ptr, nbr_idx, theta, ntheta, precision);
   if (st) return st;
   if (!loglik || !grad) return VECCHIA_EINVAL;
-  if (plan->nlarge > 0) return VECCHIA_EUNSUPPORTED;  // gradient above the register capacity
-  if (dnu && plan->engine != kEngineMfma) return VECCHIA_EUNSUPPORTED;   // Bessel form: one-wave kernels only
+  // d / d nu: the Bessel form runs on the one-wave kernels only
+  if (dnu && (plan->engine != kEngineMfma || plan->nlarge > 0)) return VECCHIA_EUNSUPPORTED;
+  // The adjoint of blocks above the one-wave limit (bv_large_kernel<T, true>)
+  // is switched off: its first GPU run ended with a device fault whose cause
+  // has not been found (a CPU emulation of its indexing stays in bounds).
+  if (plan->nlarge > 0) return VECCHIA_EUNSUPPORTED;
   if (plan->aux_ws_bytes > 0 && !plan->aux_ws) return VECCHIA_ENOMEM;
   hipStream_t s = (hipStream_t)stream;
   const int bc = (int)plan->bc;
@@ -782,6 +818,9 @@ static int loglik_grad_run(const vecchia_plan* plan, const double* locs_perm, co
   double* part = at<double>(ws, plan->off_partial);
   double* gpart = at<double>(ws, plan->off_grad);
   double* gnu = dnu ? gpart + (size_t)bc * plan->max_theta * 3 : nullptr;
+  const size_t lbytes = large_bytes(plan);
+  char* tile_ws = static_cast<char*>(plan->aux_ws) + lbytes;   // after the large-block slots
+  const size_t tile_ws_bytes = plan->aux_ws_bytes - lbytes;
   int* flag = at<int>(ws, plan->off_flag);
   int* list = at<int>(ws, plan->off_list);
   int* count = at<int>(ws, plan->off_count);
@@ -817,7 +856,7 @@ static int loglik_grad_run(const vecchia_plan* plan, const double* locs_perm, co
                          !wave_regadj(g, fp32, plan->bucket_lmax[q]);
       off[q + 1] = off[q] + (tiles ? ns * nt * wave_tile_bytes(g, fp32) : 0);
     }
-    const bool conc = plan->exec != nullptr && off[plan->nbuckets] <= plan->aux_ws_bytes;
+    const bool conc = plan->exec != nullptr && off[plan->nbuckets] <= tile_ws_bytes;
     // the largest class waits for the first factorisation launch of the split
     // (two-launch) class with the most blocks, so that the long one-wave-per-SIMD
     // factorisation items start first and the fine-grained class fills in last
@@ -840,17 +879,19 @@ static int loglik_grad_run(const vecchia_plan* plan, const double* locs_perm, co
       a.nsched = ns;
       TimingRec tr;
       VCHECK_HIP(time_begin(plan, q, sq, tr));
-      if (plan->engine == kEngineTiles)
+      if (plan->bucket_cfg[q] == kLargeCfg) {
+        const int g = ns * nt < plan->large_slots ? ns * nt : plan->large_slots;
+        VCHECK_HIP(launch_large(fp32, true, as_large(a, plan), thp, g, sq));
+      } else if (plan->engine == kEngineTiles) {
         VCHECK_ST(launch_tiles_adjoint(plan, q, fp32, a, thp, ns * nt, sq));
-      else if (conc) {
+      } else if (conc) {
         Exec* ex = static_cast<Exec*>(plan->exec);
         if (q == plan->bucket_main && qmark >= 0) VCHECK_HIP(hipStreamWaitEvent(sq, ex->mark, 0));
-        VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq,
-                                    static_cast<char*>(plan->aux_ws) + off[q], off[q + 1] - off[q],
+        VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq, tile_ws + off[q], off[q + 1] - off[q],
                                     spare_stream(plan, q), q == qmark ? ex->mark : nullptr));
+      } else {
+        VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq, tile_ws, tile_ws_bytes));
       }
-      else
-        VCHECK_ST(launch_mfma_class(plan, q, fp32, 1, a, thp, ns * nt, sq, plan->aux_ws, plan->aux_ws_bytes));
       VCHECK_HIP(time_end(plan, sq, tr));
     }
     if (conc) VCHECK_HIP(join_streams(plan, s));
@@ -870,10 +911,13 @@ static int loglik_grad_run(const vecchia_plan* plan, const double* locs_perm, co
         r.list = list + plan->bucket_off[q] * nt;
         r.list_count = count + q;
         const int cap = ns * nt;
-        if (plan->engine == kEngineTiles)
+        if (plan->bucket_cfg[q] == kLargeCfg)
+          VCHECK_HIP(launch_large(false, true, as_large(r, plan), thp, cap < plan->large_slots ? cap : plan->large_slots,
+                                  s));
+        else if (plan->engine == kEngineTiles)
           VCHECK_ST(launch_tiles_adjoint(plan, q, false, r, thp, cap < 256 ? cap : 256, s));
         else
-          VCHECK_ST(launch_mfma_class(plan, q, false, 1, r, thp, cap, s, plan->aux_ws, plan->aux_ws_bytes));
+          VCHECK_ST(launch_mfma_class(plan, q, false, 1, r, thp, cap, s, tile_ws, tile_ws_bytes));
       }
     }
     VCHECK_HIP(launch_reduce_partials(part, flag, bc, nt, fp32 ? 0 : 1, loglik + t0,

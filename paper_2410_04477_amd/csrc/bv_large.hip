@@ -7,7 +7,11 @@
 //   L_JJ = chol(C_JJ), L_IJ = C_IJ L_JJ^-T  (one thread per row)
 // The log-determinant and quadratic form come from the panel pivots and the
 // border row, as in the register kernels.  Operands stream through L2: about
-// P^3 / 96 elements are read per block.
+// P^3 / 96 elements are read per block.  The gradient variant then
+// back-substitutes the right-hand sides [w | [w_N; 0] | [0; I_l]] through L^T
+// tile row by tile row (16 x 16 triangular solves, MFMA updates of the rows
+// above) and contracts W with d K / d range regenerated from the staged
+// coordinates, as the one-wave kernels do.
 #include "internal.hpp"
 
 namespace bv {
@@ -41,11 +45,16 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-template <typename T>
+// Per-block slot layout (elements of T, P = 16 G for the block's own p):
+// the bordered matrix, column-major lower part, P x P; in gradient launches
+// the right-hand sides X (P rows, 16 ceil((l + 2) / 16) columns, column-major)
+// follow it; then the scaled coordinates of the p points (3 x P).
+template <typename T, bool GRAD>
 __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack thp) {
   typedef typename LMma<T>::acc acc_t;
   __shared__ T dtile[16][17];
   __shared__ T piv[16];
+  __shared__ double sred[2][256];
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63, lr = ln & 15, lg = ln >> 4;
   const int total = a.list ? *a.list_count : a.nsched * a.ntheta;
   T* M = reinterpret_cast<T*>(a.ws) + (size_t)blockIdx.x * a.slot_elems;
@@ -65,27 +74,31 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
     const int l = b1 - b0, m = n1 - n0, p = m + l;
     const int G = (p + 1 + 15) >> 4, P = 16 * G;
     const size_t ld = (size_t)P;
+    const int nr = l + 2, NRP = 16 * ((nr + 15) >> 4);   // right-hand sides, padded to whole tiles
+    T* X = M + ld * ld;
+    T* cs = GRAD ? X + ld * NRP : X;                      // cs[k * P + i]: scaled coordinates
     const int d = a.d;
     const MaternCoef<T> mc(th.nu_code);
     const T sig2 = T(th.sigma2), nug = T(th.nugget);
-    // ---- generate the lower part, column by column (rows over threads) -----
+    // ---- scaled coordinates relative to the block's first point -------------
     __syncthreads();
+    for (int i = tid; i < P; i += 256) {
+      const int gi = i < m ? a.nbr_idx[n0 + i] : (b0 + i - m);
+      for (int k = 0; k < 3; ++k)
+        cs[k * ld + i] = (i < p && k < d) ? T((a.locs[(size_t)gi * d + k] - a.locs[(size_t)b0 * d + k]) * th.inv_scale[k])
+                                          : T(0);
+    }
+    __syncthreads();
+    // ---- generate the lower part, column by column (rows over threads) -----
     for (int j = 0; j < P; ++j) {
       const int gj = j < m ? a.nbr_idx[n0 + j] : (b0 + j - m);
-      T cj[3] = {T(0), T(0), T(0)};
-      if (j < p)
-        for (int k = 0; k < d; ++k) cj[k] = T((a.locs[(size_t)gj * d + k] - a.locs[(size_t)b0 * d + k]) * th.inv_scale[k]);
+      const T cj0 = cs[j], cj1 = cs[ld + j], cj2 = cs[2 * ld + j];
       const T yj = j < p ? T(a.y[gj]) : T(0);
       for (int i = j + tid; i < P; i += 256) {
         T v;
         if (i < p && j < p) {
-          const int gi = i < m ? a.nbr_idx[n0 + i] : (b0 + i - m);
-          T h2 = T(0);
-          for (int k = 0; k < d; ++k) {
-            const T ci = T((a.locs[(size_t)gi * d + k] - a.locs[(size_t)b0 * d + k]) * th.inv_scale[k]);
-            h2 += (ci - cj[k]) * (ci - cj[k]);
-          }
-          v = sig2 * mc.rho(sqrt_<T>(h2)) + (i == j ? nug : T(0));
+          const T d0 = cs[i] - cj0, d1 = cs[ld + i] - cj1, d2 = cs[2 * ld + i] - cj2;
+          v = sig2 * mc.rho(sqrt_<T>(d0 * d0 + d1 * d1 + d2 * d2)) + (i == j ? nug : T(0));
         } else if (i == p && j < p) {
           v = yj;
         } else {
@@ -98,7 +111,7 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
     const double guard = a.fp32_guard == 2 ? INFINITY
         : a.fp32_guard ? fmax(0.5 * th.nugget, (double)p * 1.1920928955078125e-07 * (th.sigma2 + th.nugget))
         : 0.0;
-    double acc_ll = 0.0;
+    double acc_ll = 0.0, qb = 0.0;
     int flag = 0;
     const int Gp = (p + 15) >> 4;  // panels holding real columns
     for (int J = 0; J < Gp; ++J) {
@@ -174,25 +187,148 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
             if (k >= m) {
               const double wk = (double)M[(size_t)k * ld + p];
               acc_ll += log(dd) + wk * wk;
+              qb += wk * wk;
             }
           }
         }
       }
       __syncthreads();
     }
+    const size_t o = (size_t)tt * a.bc + b;
     if (tid == 0) {
-      const size_t o = (size_t)tt * a.bc + b;
       a.partial[o] = (flag & 2) && !a.fp32_guard ? __builtin_nan("") : -0.5 * (acc_ll + (double)l * kLog2Pi);
       a.flag[o] = flag | a.flag_or;
+    }
+    if constexpr (GRAD) {
+      // ---- adjoint: X = L^-T [w | [w_N; 0] | [0; I_l]], then the contraction of
+      // W = alpha alpha^T - b b^T - X_R X_R^T with d K / d range (d / d sigma2
+      // from the quadratic forms and tr W, d / d nugget = tr W / 2), as in the
+      // one-wave kernels.  The border row of the factor (row p) holds w.
+      for (size_t e = tid; e < ld * NRP; e += 256) {
+        const int c = (int)(e / ld), row = (int)(e - (size_t)c * ld);
+        T v = T(0);
+        if (row < p) {
+          if (c == 0 || (c == 1 && row < m)) v = M[(size_t)row * ld + p];
+          else if (c >= 2 && row == m + c - 2) v = T(1);
+        }
+        X[e] = v;
+      }
+      __threadfence_block();
+      __syncthreads();
+      for (int K = Gp - 1; K >= 0; --K) {
+        // L_KK to LDS (padding columns of the factor are identity)
+        for (int e = tid; e < 256; e += 256) {
+          const int r = e & 15, c = e >> 4;
+          dtile[r][c] = r >= c ? M[(size_t)(K * 16 + c) * ld + K * 16 + r] : T(0);
+        }
+        __syncthreads();
+        // X_K <- L_KK^-T X_K, one column per thread (back-substitution)
+        for (int c = tid; c < NRP; c += 256) {
+          T x[16];
+#pragma unroll
+          for (int r = 0; r < 16; ++r) x[r] = X[(size_t)c * ld + K * 16 + r];
+#pragma unroll
+          for (int r = 15; r >= 0; --r) {
+            T v = x[r];
+#pragma unroll
+            for (int t = r + 1; t < 16; ++t) v -= dtile[t][r] * x[t];
+            x[r] = v / dtile[r][r];
+          }
+#pragma unroll
+          for (int r = 0; r < 16; ++r) X[(size_t)c * ld + K * 16 + r] = x[r];
+        }
+        __threadfence_block();
+        __syncthreads();
+        // X_J -= L_KJ^T X_K for J < K: 16 x 16 output tiles (J, q) dealt to the waves
+        const int nq = NRP >> 4;
+        for (int e = wv; e < K * nq; e += 4) {
+          const int J = e / nq, q = e - J * nq;
+          acc_t c;
+#pragma unroll
+          for (int r = 0; r < 4; ++r) c[r] = X[(size_t)(q * 16 + lr) * ld + J * 16 + LMma<T>::row(lg, r)];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) {
+            const int t = K * 16 + 4 * s + lg;
+            const T av = -M[(size_t)(J * 16 + lr) * ld + t];   // L[t][J*16 + i]
+            const T bv = X[(size_t)(q * 16 + lr) * ld + t];
+            c = LMma<T>::op(av, bv, c);
+          }
+#pragma unroll
+          for (int r = 0; r < 4; ++r) X[(size_t)(q * 16 + lr) * ld + J * 16 + LMma<T>::row(lg, r)] = c[r];
+        }
+        __threadfence_block();
+        __syncthreads();
+      }
+      // contraction over the tile pairs (I, J), J <= I < Gp, dealt to the waves
+      const T irange = T(th.inv_range);
+      double g1 = 0.0, g2 = 0.0;
+      const int npair = Gp * (Gp + 1) / 2;
+      for (int e = wv; e < npair; e += 4) {
+        int I = 0;
+        while ((I + 1) * (I + 2) / 2 <= e) ++I;
+        const int J = e - I * (I + 1) / 2;
+        acc_t w;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) w[r] = T(0);
+        for (int c0 = 0; c0 < NRP; c0 += 4) {
+          const int c = c0 + lg;
+          const T av = (c == 0 ? T(1) : T(-1)) * X[(size_t)c * ld + I * 16 + lr];
+          const T bv = X[(size_t)c * ld + J * 16 + lr];
+          w = LMma<T>::op(av, bv, w);
+        }
+        const int j = J * 16 + lr;
+        const T sj0 = cs[j], sj1 = cs[ld + j], sj2 = cs[2 * ld + j];
+        T s1 = T(0), s2 = T(0);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = I * 16 + LMma<T>::row(lg, r);
+          if (i < p && j < p) {
+            const T d0 = cs[i] - sj0, d1 = cs[ld + i] - sj1, d2 = cs[2 * ld + i] - sj2;
+            s1 += w[r] * mc.drange(sqrt_<T>(d0 * d0 + d1 * d1 + d2 * d2), irange);
+            if (i == j) s2 += w[r];
+          }
+        }
+        g1 += (I == J ? 1.0 : 2.0) * (double)s1;
+        g2 += (double)s2;
+      }
+      sred[0][tid] = g1;
+      sred[1][tid] = g2;
+      __syncthreads();
+      for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+          sred[0][tid] += sred[0][tid + h];
+          sred[1][tid] += sred[1][tid + h];
+        }
+        __syncthreads();
+      }
+      if (tid == 0) {
+        const bool bad = (flag & 2) && !a.fp32_guard;
+        const double tr = sred[1][0];
+        a.gpart[3 * o + 0] = bad ? __builtin_nan("") : 0.5 * (qb - (double)l - th.nugget * tr) / th.sigma2;
+        a.gpart[3 * o + 1] = bad ? __builtin_nan("") : 0.5 * th.sigma2 * sred[0][0];
+        a.gpart[3 * o + 2] = bad ? __builtin_nan("") : 0.5 * tr;
+      }
+      __syncthreads();
     }
   }
 }
 
-hipError_t launch_large(bool fp32, const LargeArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
-  if (fp32)
-    hipLaunchKernelGGL((bv_large_kernel<float>), dim3(grid), dim3(256), 0, s, a, thp);
-  else
-    hipLaunchKernelGGL((bv_large_kernel<double>), dim3(grid), dim3(256), 0, s, a, thp);
+// slot elements of a large block with pmax joint rows and lmax block rows,
+// with the gradient's right-hand sides
+size_t large_slot_elems(int pmax, int lmax) {
+  const size_t P = 16 * (size_t)((pmax + 1 + 15) / 16);
+  const size_t nrp = 16 * (size_t)((lmax + 2 + 15) / 16);
+  return P * (P + nrp) + 3 * P;
+}
+
+hipError_t launch_large(bool fp32, bool grad, const LargeArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
+  if (fp32) {
+    if (grad) hipLaunchKernelGGL((bv_large_kernel<float, true>), dim3(grid), dim3(256), 0, s, a, thp);
+    else hipLaunchKernelGGL((bv_large_kernel<float, false>), dim3(grid), dim3(256), 0, s, a, thp);
+  } else {
+    if (grad) hipLaunchKernelGGL((bv_large_kernel<double, true>), dim3(grid), dim3(256), 0, s, a, thp);
+    else hipLaunchKernelGGL((bv_large_kernel<double, false>), dim3(grid), dim3(256), 0, s, a, thp);
+  }
   return hipGetLastError();
 }
 

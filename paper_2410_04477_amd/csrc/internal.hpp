@@ -119,12 +119,16 @@ struct LargeArgs {
   int fp32_guard;
   int flag_or;
   void* ws;              // nslots x slot_elems elements
-  int64_t slot_elems;    // P_max^2
+  int64_t slot_elems;    // large_slot_elems(p_max, l_max)
   double* partial;
   int* flag;
+  double* gpart;         // gradient launches: [(theta * bc + block) * 3 + k]
 };
 constexpr int kLargeCfg = 31;   // size class of blocks above the register capacity
-hipError_t launch_large(bool fp32, const LargeArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
+// elements of one large-block slot: the P x P matrix, the gradient's P x 16 ceil((l + 2) / 16)
+// right-hand sides and 3 P staged coordinates, P = 16 ceil((p_max + 1) / 16)
+size_t large_slot_elems(int pmax, int lmax);
+hipError_t launch_large(bool fp32, bool grad, const LargeArgs& a, const ThetaPack& thp, int grid, hipStream_t s);
 
 // leading dimension of the LDS right-hand sides for l_max (matrix-core engine)
 inline int mfma_ldx(int nr_max) { return 16 * ((nr_max + 15) / 16) + 1; }
