@@ -24,6 +24,8 @@ class MLEResult:
     iters: int
     seconds: float
     converged: bool
+    grad_eta: float = math.nan   # max |d l / d eta_k| / n at theta, FP64 adjoint
+    restarts: int = 0
 
 
 def _nu_to_eta(nu: float) -> float:
@@ -50,8 +52,52 @@ def to_eta(theta, estimate_nu: bool = False) -> list:
     return e
 
 
+def stationarity(model: BlockVecchia, theta, estimate_nu: bool = False) -> float:
+    """max_k |d l / d eta_k| / n at theta from the FP64 adjoint, eta the
+    unconstrained parameters of fit (so a nugget driven to zero, where
+    d l / d eta_3 = nugget d l / d nugget vanishes, counts as stationary)."""
+    th = tuple(float(v) for v in theta)
+    if estimate_nu:
+        _, g, _, _, _ = model.loglik_grad_nu([model.theta(*th)], "fp64")
+    else:
+        _, g, _, _, _ = model.loglik_grad([model.theta(*th)], "fp64")
+    g = g[0].cpu().numpy()
+    ge = [g[k] * th[k] for k in range(3)]
+    if estimate_nu:
+        u = (th[3] - NU_LO) / (NU_HI - NU_LO)
+        ge.append(g[3] * (NU_HI - NU_LO) * u * (1.0 - u))
+    return float(max(abs(v) for v in ge)) / model.n
+
+
 def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 200, tol_rel: float = 1e-10,
-        history: int = 10, polish_evals: int = 30, estimate_nu: bool = False) -> MLEResult:
+        history: int = 10, polish_evals: int = 30, estimate_nu: bool = False, restarts: int = 3,
+        stat_tol: float = 1e-7) -> MLEResult:
+    """L-BFGS MLE (see _fit_once), then a stationarity check with the FP64
+    adjoint: while max_k |d l / d eta_k| / n exceeds stat_tol, L-BFGS starts
+    again in FP64 from the point reached (fresh curvature history), at most
+    `restarts` times.  The line search of a long run can stop on a tiny
+    relative change of the objective while the gradient is still clearly
+    non-zero; a fresh start from there continues the ascent."""
+    res = _fit_once(model, theta0, precision, max_evals, tol_rel, history, polish_evals, estimate_nu)
+    res.grad_eta = stationarity(model, res.theta, estimate_nu)
+    for k in range(restarts):
+        if not res.grad_eta > stat_tol:
+            break
+        # torch's L-BFGS stops on an absolute change of the objective below
+        # tolerance_change, which near a flat optimum can come before the
+        # gradient is small: the restart asks for a far smaller change
+        more = _fit_once(model, res.theta, "fp64", max(polish_evals, max_evals // 2), tol_rel * 1e-4, history, 0,
+                         estimate_nu)
+        better = more.loglik >= res.loglik
+        res = MLEResult(more.theta if better else res.theta, max(more.loglik, res.loglik), res.evals + more.evals,
+                        res.iters + more.iters, res.seconds + more.seconds, more.converged if better else res.converged,
+                        restarts=k + 1)
+        res.grad_eta = stationarity(model, res.theta, estimate_nu)
+    return res
+
+
+def _fit_once(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 200, tol_rel: float = 1e-10,
+              history: int = 10, polish_evals: int = 30, estimate_nu: bool = False) -> MLEResult:
     """L-BFGS (strong Wolfe line search) on eta = log(sigma2, range, nugget),
     minimising -l / n.  Stops on relative change < tol_rel, small gradient, or
     max_evals evaluations.  With an FP32-bulk precision, a short FP64 L-BFGS
@@ -62,8 +108,8 @@ def fit(model: BlockVecchia, theta0, precision: str = "fp64", max_evals: int = 2
     others), through eta_4 = logit((nu - NU_LO) / (NU_HI - NU_LO)); theta0 may
     then carry a fourth entry, the starting nu (else the model's)."""
     if precision != "fp64" and polish_evals > 0:
-        first = fit(model, theta0, precision, max_evals, tol_rel, history, 0, estimate_nu)
-        second = fit(model, first.theta, "fp64", polish_evals, tol_rel, history, 0, estimate_nu)
+        first = _fit_once(model, theta0, precision, max_evals, tol_rel, history, 0, estimate_nu)
+        second = _fit_once(model, first.theta, "fp64", polish_evals, tol_rel, history, 0, estimate_nu)
         return MLEResult(second.theta, second.loglik, first.evals + second.evals, first.iters + second.iters,
                          first.seconds + second.seconds, second.converged)
     if estimate_nu:

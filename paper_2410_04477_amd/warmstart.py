@@ -231,7 +231,9 @@ def run_experiment(n_train_sets: int = 4096, n_train: int = 20_000, n_designs: i
         llc = float(mod.loglik([mod.theta(*rc.theta)], "fp64")[0][0])
         rows.append(dict(nu=th.nu, truth=(th.sigma2, th.beta, th.nugget), start=start, used_net=used_net,
                          warm_theta=rw.theta, cold_theta=rc.theta, warm_evals=rw.evals, cold_evals=rc.evals,
-                         warm_s=rw.seconds + t_pred, cold_s=rc.seconds, warm_loglik=llw, cold_loglik=llc))
+                         warm_s=rw.seconds + t_pred, cold_s=rc.seconds, warm_loglik=llw, cold_loglik=llc,
+                         warm_grad_eta=rw.grad_eta, cold_grad_eta=rc.grad_eta, warm_restarts=rw.restarts,
+                         cold_restarts=rc.restarts))
         if i % 16 == 0:
             log(f"[warmstart] test {i}: warm {rw.evals} evals {rw.seconds:.2f}s ll {llw:.3f} | "
                 f"cold {rc.evals} evals {rc.seconds:.2f}s ll {llc:.3f}")
@@ -250,6 +252,10 @@ def run_experiment(n_train_sets: int = 4096, n_train: int = 20_000, n_designs: i
         "net_used_fraction": float(np.mean([r["used_net"] for r in rows])),
         "rel_loglik_gap_warm_minus_cold": {"min": float(gap.min()), "median": float(np.median(gap)),
                                            "max": float(gap.max())},
+        "max_grad_eta_per_n": {"warm": float(max(r["warm_grad_eta"] for r in rows)),
+                               "cold": float(max(r["cold_grad_eta"] for r in rows))},
+        "restarted_fits": {"warm": int(sum(r["warm_restarts"] > 0 for r in rows)),
+                           "cold": int(sum(r["cold_restarts"] > 0 for r in rows))},
         "rows": rows,
     }
 

@@ -133,6 +133,8 @@ def test_training_reduces_loss_and_warm_start_helps():
         evals_w.append(rw.evals)
         evals_c.append(rc.evals)
         gap.append((rw.loglik - rc.loglik) / abs(rc.loglik))
+        # both fits end stationary by the FP64 adjoint (mle.fit restarts L-BFGS while they are not)
+        assert rw.grad_eta <= 1e-6 and rc.grad_eta <= 1e-6, (rw, rc)
     print("warm evals", evals_w, "cold evals", evals_c, "rel loglik gap", gap)
     assert np.median(evals_w) <= np.median(evals_c)
-    assert min(gap) >= -1e-4   # warm start ends at least as likely (to tolerance)
+    assert min(gap) >= -1e-6   # warm start ends at least as likely (to tolerance)
