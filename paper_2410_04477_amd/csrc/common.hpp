@@ -244,6 +244,13 @@ struct MaternCoef {
   __device__ __forceinline__ T drange(T x, T inv_range) const {
     return x * inv_range * expneg<T>(x) * (g0 + x * (g1 + g2 * x));
   }
+  // -(sigma2 rho(x)) with the scale and sign folded into the coefficients
+  // (s0, s1, s2) = -sigma2 (1, c1, c2)
+  __device__ __forceinline__ T neg_cov(T x, T s0, T s1, T s2) const { return expneg<T>(x) * (s0 + x * (s1 + s2 * x)); }
+  // d rho / d range with 1 / range folded into (h0, h1, h2) = (g0, g1, g2) / range
+  __device__ __forceinline__ T drange_scaled(T x, T h0, T h1, T h2) const {
+    return x * expneg<T>(x) * (h0 + x * (h1 + h2 * x));
+  }
 };
 
 // The correlation a kernel generates: closed forms (GEN = false), or the

@@ -184,6 +184,14 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 
   // ---- generate the bordered joint matrix in the accumulator tiles ----------
   const T sig2 = T(th.sigma2), nug = T(th.nugget);
+  // closed forms: -sigma2 (1 + c1 x + c2 x^2) e^-x with the scale and sign in
+  // the coefficients
+  T ns0 = T(0), ns1 = T(0), ns2 = T(0);
+  if constexpr (!GEN) {
+    ns0 = -sig2;
+    ns1 = -sig2 * mc.c1;
+    ns2 = -sig2 * mc.c2;
+  }
   static_for<0, G>(BV_CI(I) {
     BV_CV(I);
     T ri[4][3];
@@ -203,9 +211,13 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         const int i = I * 16 + M::row(lg, r);
         const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
         const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
-        T v = sig2 * mc.rho(x) + ((i == j) ? nug : T(0));
-        if (!(real_row(i) && real_row(j))) v = (i == j) ? T(1) : T(0);
-        acc[tix(I, J)][r] = -v;   // the tiles hold the negated matrix (updates add L L^T)
+        // the tiles hold the negated matrix (updates add L L^T)
+        T v;
+        if constexpr (GEN) v = -(sig2 * mc.rho(x));
+        else v = mc.neg_cov(x, ns0, ns1, ns2);
+        if constexpr (I == J) v -= (i == j) ? nug : T(0);   // the nugget: same-index pairs only
+        if (!(real_row(i) && real_row(j))) v = (i == j) ? T(-1) : T(0);
+        acc[tix(I, J)][r] = v;
       }
       if (I == (p >> 4)) {  // border row p: y_J
         const T yb = sy[j];
@@ -455,6 +467,12 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   T* X = work;   // X[row * LDX + col], one chunk of right-hand sides
 
   const T irange = T(th.inv_range);
+  T dh0 = T(0), dh1 = T(0), dh2 = T(0);   // closed forms: d rho / d range coefficients over the range
+  if constexpr (!GEN) {
+    dh0 = mc.g0 * irange;
+    dh1 = mc.g1 * irange;
+    dh2 = mc.g2 * irange;
+  }
   // d/d sigma2 needs no entry of dK: with d K_J / d sigma2 = (K_J - nugget I) / sigma2,
   // <W, K_J> = ||w||^2 - ||w_N||^2 - l (the quadratic forms of y_J and y_N, and
   // tr(X_R^T K_J X_R) = l) and tr W = 2 d l / d nugget, so that
@@ -510,7 +528,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
               s1 += c[r] * mc.drange(x, irange);
             }
           } else {
-            s1 += c[r] * mc.drange(x, irange);
+            s1 += c[r] * mc.drange_scaled(x, dh0, dh1, dh2);
           }
         };
         if ((I + 1) * 16 <= p) {   // a tile inside the point rows (wave-uniform)
