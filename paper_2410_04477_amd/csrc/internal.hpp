@@ -76,8 +76,9 @@ constexpr int kWaveChunk = 32;  // adjoint right-hand sides per pass, at most (b
 // right-hand sides per pass of a class with g tile rows: 28 up to g = 9, which
 // keeps the one-wave adjoint's LDS at or under 20 kB (eight waves per CU)
 __host__ __device__ constexpr int wave_chunk(int g) { return g <= 9 ? 28 : kWaveChunk; }
-// bytes of one work item's factor tiles in the adjoint's tile buffer, and the buffer's cap
-inline size_t wave_tile_bytes(int g, bool fp32) { return (size_t)g * (g + 1) / 2 * 256 * (fp32 ? 4 : 8); }
+// bytes of one work item's slot in the adjoint's tile buffer (factor tiles and
+// the border row), and the buffer's cap
+inline size_t wave_tile_bytes(int g, bool fp32) { return ((size_t)g * (g + 1) / 2 * 256 + 16 * (size_t)g) * (fp32 ? 4 : 8); }
 constexpr size_t kAdjTileCap = (size_t)4 << 30;
 bool wave_fits(int g, bool fp32);
 // gradient as two launches (factor + tiles, then the adjoint from the tiles)

@@ -88,16 +88,21 @@ __host__ __device__ constexpr int tix(int I, int J) { return I * (I + 1) / 2 + J
 
 constexpr int kStageStride = 260;   // staged 16 x 16 tiles, padded so tiles four apart fall in different banks
 
+__host__ __device__ constexpr int wave_max(int x, int y) { return x > y ? x : y; }
+
 __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
-  // su (3 P) for the whole kernel, then a work region: the panel (4 P) and sy,
-  // sdk, swk (P each) during the factorisation; for the adjoint, one chunk of
-  // right-hand sides (P x (wave_chunk(G) + 1), plus 32 elements that reads of
-  // the last row's unused columns may touch), which also holds the G staged
-  // diagonal tiles before the first chunk
-  return 3 * 16 * G + (mode == 0 || mode == 2 || mode == 4 ? 7 * 16 * G
-                                              : (16 * (wave_chunk(G) + 1) > kStageStride
-                                                     ? 16 * G * (wave_chunk(G) + 1) + 32
-                                                     : G * kStageStride));
+  // su (3 P) for the whole kernel, then a work region: the panel (4 columns of
+  // P rows, plus 16 appended rows in the modes that form the diagonal inverses
+  // during the factorisation) and sy, sdk, swk (P each) during the
+  // factorisation; for the adjoint, one chunk of right-hand sides
+  // (P x (wave_chunk(G) + 1), plus 32 elements that reads of the last row's
+  // unused columns may touch), which also holds the G staged diagonal tiles
+  // before the first chunk
+  return 3 * 16 * G + wave_max(4 * (16 * G + (mode == 2 || mode == 5 ? 16 : 0)) + 3 * 16 * G,
+                               mode == 0 || mode == 2 || mode == 4 ? 0
+                               : (16 * (wave_chunk(G) + 1) > kStageStride
+                                      ? 16 * G * (wave_chunk(G) + 1) + 32
+                                      : G * kStageStride));
 }
 
 template <typename T, int G, int MODE>
@@ -125,7 +130,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   T* work = su + 3 * P;
   // MODE 5 appends 16 rows to the panel (the identity rows whose elimination
   // gives the inverse of each diagonal tile of the factor)
-  constexpr int PS = MODE == 5 ? P + 16 : P;   // panel column stride
+  constexpr bool EINV = MODE == 5 || MODE == 2;   // diagonal inverses formed during the factorisation
+  constexpr int PS = EINV ? P + 16 : P;            // panel column stride
+  static_assert(3 * P + 4 * PS + 3 * P <= wave_lds_elems(G, MODE), "factorisation LDS");
   T* sy = work + 4 * PS;               // border row y_J
   T* sdk = sy + P;                     // pivots d_k
   T* swk = sdk + P;                    // border entries w_k
@@ -175,7 +182,10 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   }
   __syncthreads();
   const size_t o = (size_t)tt * a.bc + b;
-  T* Lg = reinterpret_cast<T*>(a.tiles) + (size_t)(wi - a.item_base) * (NT * 256);   // tile slot (MODE 1-3)
+  // tile slot (MODE 1-3): the NT factor tiles (MODE 2: the diagonal ones
+  // replaced by their inverses), then the border row w (16 G elements)
+  constexpr int SLOT = NT * 256 + 16 * G;
+  T* Lg = reinterpret_cast<T*>(a.tiles) + (size_t)(wi - a.item_base) * SLOT;
   double acc_ll = 0.0;
   int flag = 0;
   const MaternF<T, GEN> mc(th);
@@ -233,7 +243,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 
   // ---- factorisation, four columns per step -----------------------------------
   T* pan = work;  // pan[c * PS + row], c < 4
-  // MODE 5: the 16 rows appended below the matrix while tile column K is
+  // MODES 5 and 2: the 16 rows appended below the matrix while tile column K is
   // eliminated, R = e_j^T at column 16 K + j (zero left of the tile column,
   // so earlier columns leave them untouched).  After the tile column they hold
   // R L_KK^-T = L_KK^-T, and the transpose of that, inv(L_KK), replaces L_KK
@@ -249,7 +259,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 #pragma unroll
         for (int r = 0; r < 4; ++r) pan[(lr - c0) * PS + I * 16 + M::row(lg, r)] = acc[tix(I, Kc)][r];
       });
-      if (MODE == 5) {
+      if (EINV) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) pan[(lr - c0) * PS + P + M::row(lg, r)] = einv[r];
       }
@@ -321,7 +331,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   static_for<0, G>(BV_CI(K) {
     BV_CV(K);
     if (K * 16 >= kend) return;
-    if constexpr (MODE == 5) {
+    if constexpr (EINV) {
       // -e_j for the columns the loop below eliminates; columns it skips (at
       // and beyond kend: the border column and the padding) keep +e_j, the
       // identity of the inverse there
@@ -349,7 +359,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
           acc[tix(I, J)] = M::op(v[I], v[J], acc[tix(I, J)]);
         });
       });
-      if (MODE == 5) einv = M::op(pan[lg * PS + P + lr], v[K], einv);
+      if (EINV) einv = M::op(pan[lg * PS + P + lr], v[K], einv);
       if (MODE != 0 && MODE != 4 && lr >= c0 && lr < c0 + 4) {
         // keep the finished factor columns in the tiles
         static_for<K, G>(BV_CI(I) {
@@ -357,14 +367,14 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 #pragma unroll
           for (int r = 0; r < 4; ++r) acc[tix(I, K)][r] = pan[(lr - c0) * PS + I * 16 + M::row(lg, r)];
         });
-        if (MODE == 5) {
+        if (EINV) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) einv[r] = pan[(lr - c0) * PS + P + M::row(lg, r)];
         }
       }
       __syncthreads();
     }
-    if constexpr (MODE == 5) {
+    if constexpr (EINV) {
       // inv(L_KK) = (L_KK^-T)^T into the diagonal tile, transposed through LDS
 #pragma unroll
       for (int r = 0; r < 4; ++r) pan[lr * 16 + M::row(lg, r)] = einv[r];
@@ -447,6 +457,8 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 #pragma unroll
       for (int r = 0; r < 4; ++r) Lg[t * 256 + ln * 4 + r] = acc[t][r];
     });
+    // the border row w = L^-1 y_J (the diagonal tiles no longer hold it in MODE 2)
+    for (int j = ln; j < P; j += 64) Lg[NT * 256 + j] = j < p ? swk[j] : T(0);
     __syncthreads();
   }
   if (MODE == 2) return;
@@ -462,7 +474,6 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   auto colok = [&](int q) __attribute__((always_inline)) { return (q + 1) * 16 <= CH || q * 16 + lr < CH; };
   constexpr int GM = G > 1 ? G - 1 : 1;   // tile rows above a diagonal step, at most
   const int nr = l + 2;
-  const int Ip = p >> 4, rp = p & 15;
   const int Gp = (p + 15) >> 4;
   T* X = work;   // X[row * LDX + col], one chunk of right-hand sides
 
@@ -639,18 +650,19 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     });
     contract(0, nr);
   } else {
-  // border row p of the bordered factor: w = L^-1 y_J (read before the
-  // diagonal tiles are replaced by their inverses)
+  // border row p of the bordered factor: w = L^-1 y_J, stored after the tiles
   constexpr int NW = (P + 63) / 64;
   T wreg[NW];
 #pragma unroll
   for (int k = 0; k < NW; ++k) {
     const int j = ln + 64 * k;
-    wreg[k] = j < p ? Lg[(Ip * (Ip + 1) / 2 + (j >> 4)) * 256 + M::at(rp, j & 15)] : T(0);
+    wreg[k] = j < p ? Lg[NT * 256 + j] : T(0);
     if (j >= m && j < p) qb += (double)wreg[k] * (double)wreg[k];
   }
 
-  // ---- inverses of the diagonal 16 x 16 blocks of L ---------------------------
+  // ---- inverses of the diagonal 16 x 16 blocks of L (MODE 1; MODE 3 reads the
+  // ones its factorisation launch formed) ---------------------------------------
+  if constexpr (MODE == 1) {
   // all Gp blocks staged at once (the border row and the padding become
   // identity rows); lane (c = l % 16, g = l / 16) forms column c of inv(L_KK)
   // for K = g, g + 4, g + 8 by forward substitution, three independent chains
@@ -696,6 +708,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       }
     }
   }
+  }   // MODE 1
   __syncthreads();
 
   // ---- X <- L^-T X and the contraction, CH right-hand sides per pass ---------
