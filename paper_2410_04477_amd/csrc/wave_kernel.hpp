@@ -293,29 +293,55 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       }
     }
     const int i0 = k0 & ~15;
+    constexpr int NCH = (PS + 63) / 64;   // 64-row chunks of the panel
+    // every chunk's entries are read before any is used (the row index is
+    // clamped into the panel; the clamped lanes store nothing)
+    T pv[NCH][4];
 #pragma unroll
-    for (int q = 0; q < (PS + 63) / 64; ++q) {
+    for (int q = 0; q < NCH; ++q) {
+      const int i = i0 + ln + 64 * q;
+      const int ic = i < PS ? i : PS - 1;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) pv[q][c] = pan[c * PS + ic];
+    }
+#pragma unroll
+    for (int q = 0; q < NCH; ++q) {
       const int i = i0 + ln + 64 * q;
       if (i < PS) {
-        // branch-free: every lane runs the substitution, which also yields the
-        // rows of the diagonal block up to their diagonal (the operations that
-        // formed Ld); right of the diagonal there, and above the block, is zero.
-        // An appended row j stands for column i0 + j: identity at the padding.
-        const int di = (i < P ? i : i0 + (i - P)) - k0;
+        // every lane runs the substitution, which also yields the rows of the
+        // diagonal block up to their diagonal (the operations that formed Ld);
+        // right of the diagonal there, and above the block, is zero.  Only the
+        // first chunk holds such rows (i0 + 64 > k0 + 3).  An appended row j
+        // stands for column i0 + j.
         T x[4];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          T v = -pan[c * PS + i];
+          T v = -pv[q][c];
 #pragma unroll
           for (int j = 0; j < c; ++j) v -= x[j] * Ld[c][j];
-          const T t = di < c && i < P ? T(0) : v * rinv[c];
-          x[c] = (k0 + c < p) ? t : (di == c ? T(1) : T(0));   // padding columns: identity
+          x[c] = v * rinv[c];
+          if (q == 0) x[c] = (i < P ? i : i0 + (i - P)) - k0 < c && i < P ? T(0) : x[c];
         }
 #pragma unroll
         for (int c = 0; c < 4; ++c) pan[c * PS + i] = x[c];
         if (i == p) {
 #pragma unroll
           for (int c = 0; c < 4; ++c) swk[k0 + c] = x[c];
+        }
+      }
+    }
+    if (k0 + 4 > p) {
+      // the panel holds padding columns (at and beyond p, the last ones): they
+      // become identity columns.  What the substitution wrote there fed only
+      // later columns of the panel, which are padding too.
+#pragma unroll
+      for (int q = 0; q < NCH; ++q) {
+        const int i = i0 + ln + 64 * q;
+        if (i < PS) {
+          const int di = (i < P ? i : i0 + (i - P)) - k0;
+#pragma unroll
+          for (int c = 0; c < 4; ++c)
+            if (k0 + c >= p) pan[c * PS + i] = di == c ? T(1) : T(0);
         }
       }
     }
@@ -511,12 +537,17 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         ri[r][2] = su[2 * P + i];
       }
       auto wtile = [&](int J) __attribute__((always_inline)) {
+        // all B operands are read before the first product (the reads stay in
+        // the row: 4 kq + lg < CH), so the chain waits for LDS once
+        T xb[CH / 4];
+#pragma unroll
+        for (int kq = 0; kq < CH / 4; ++kq) xb[kq] = X[(J * 16 + lr) * LDX + 4 * kq + lg];
         acc_t c;
 #pragma unroll
         for (int r = 0; r < 4; ++r) c[r] = T(0);
 #pragma unroll
         for (int kq = 0; kq < CH / 4; ++kq)
-          if (kq < nk) c = M::op(av[kq], X[(J * 16 + lr) * LDX + 4 * kq + lg], c);
+          if (kq < nk) c = M::op(av[kq], xb[kq], c);
         return c;
       };
       acc_t cn = wtile(0);
@@ -578,7 +609,6 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     }
     __syncthreads();
     // right-hand sides [ w | [z; 0] | [0; I_l] ] (nr <= CH: one pass)
-    const int nq = (nr + 15) >> 4;
     for (int e = ln; e < P * LDX + 32; e += 64) X[e] = T(0);
     __syncthreads();
     for (int c = ln; c < nr; c += 64)
@@ -598,25 +628,27 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     // register s, i.e. row M::row(k, s) of the tile, and the B operand takes
     // the same row of X.  The diagonal step's result, in accumulator layout,
     // is then directly the B operand of the updates of the rows above.
+    // (all NQ column tiles every step: the columns at and beyond nr are zero
+    // and stay zero, so no step branches on the chunk width)
     static_for_down<0, G>(BV_CI(K) {
       BV_CV(K);
       if (K >= Gp) return;
       acc_t dq[NQ];
+      T xb[NQ][4];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+#pragma unroll
+        for (int sb = 0; sb < 4; ++sb) xb[q][sb] = X[(K * 16 + M::row(lg, sb)) * LDX + q * 16 + lr];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) dq[q][r] = T(0);
-        if (q < nq) {
-          T xb[4];
 #pragma unroll
-          for (int sb = 0; sb < 4; ++sb) xb[sb] = X[(K * 16 + M::row(lg, sb)) * LDX + q * 16 + lr];
-#pragma unroll
-          for (int sb = 0; sb < 4; ++sb) dq[q] = M::op(acc[tix(K, K)][sb], xb[sb], dq[q]);
-        }
+        for (int sb = 0; sb < 4; ++sb) dq[q] = M::op(acc[tix(K, K)][sb], xb[q][sb], dq[q]);
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q)
-        if (q < nq && colok(q)) {
+        if (colok(q)) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) X[(K * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = dq[q][r];
         }
@@ -630,18 +662,15 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         acc_t cj[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-          if (q < nq) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) cj[q][r] = X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr];
-          }
+          for (int r = 0; r < 4; ++r) cj[q][r] = X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr];
 #pragma unroll
         for (int sb = 0; sb < 4; ++sb)
 #pragma unroll
-          for (int q = 0; q < NQ; ++q)
-            if (q < nq) cj[q] = M::op(acc[tix(K, J)][sb], dq[q][sb], cj[q]);
+          for (int q = 0; q < NQ; ++q) cj[q] = M::op(acc[tix(K, J)][sb], dq[q][sb], cj[q]);
 #pragma unroll
         for (int q = 0; q < NQ; ++q)
-          if (q < nq && colok(q)) {
+          if (colok(q)) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = cj[q][r];
           }
