@@ -177,11 +177,13 @@ int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_t d, const 
  *   16 x 16 matrix-core accumulator tiles of ONE wave (a 64-thread workgroup).
  *   The Cholesky runs in panels of four columns with rank-4 MFMA updates; the
  *   adjoint's back-substitution and contraction are MFMA products.  Up to
- *   G = 9 tile rows, when l_i + 2 right-hand sides fit one pass (28), the
- *   factor stays in the registers through the adjoint (the inverses of its
- *   diagonal tiles are formed during the factorisation); otherwise the factor
- *   goes to the auxiliary tile buffer and the right-hand sides run in passes
- *   of up to 32, so any l_i fits the LDS.  FP64 classes above G = 9 exceed the
+ *   G = 9 tile rows (FP64) or G = 10 (FP32) the factor stays in the registers
+ *   through the adjoint (the inverses of its diagonal tiles are formed during
+ *   the factorisation) and the l_i + 2 right-hand sides run in passes of 28
+ *   (32 at G = 10); at G = 9 only when they fit one pass.  Otherwise the
+ *   factor goes to the auxiliary tile buffer (FP32 G = 11: a factorisation
+ *   launch, then an adjoint launch) and the right-hand sides run in passes of
+ *   up to 32, so any l_i fits the LDS.  FP64 classes above G = 9 exceed the
  *   register file and spill part of the tiles.
  * VECCHIA_ENGINE_MFMA_WG: the same tiles spread over the four waves of a
  *   workgroup, for every size class (two barriers per panel).

@@ -863,7 +863,7 @@ static int loglik_grad_run(const vecchia_plan* plan, const double* locs_perm, co
     int qmark = -1;
     if (conc && plan->engine == kEngineMfma)
       for (int q = 0; q < plan->nbuckets; ++q)
-        if (q != plan->bucket_main && wave_split(plan->bucket_cfg[q] + 1, fp32) &&
+        if (q != plan->bucket_main && plan->bucket_cfg[q] != kLargeCfg && class_wave_mode(plan, q, fp32, true) == 23 &&
             (qmark < 0 || plan->bucket_off[q + 1] - plan->bucket_off[q] >
                               plan->bucket_off[qmark + 1] - plan->bucket_off[qmark]))
           qmark = q;

@@ -10,6 +10,8 @@ namespace bv {
 
 constexpr int kMaxThetaPerLaunch = 24;   // theta values passed by value in kernel arguments
 constexpr double kLog2Pi = 1.83787706640934548356065947281123527;
+constexpr double kLn2 = 0.693147180559945309417232121458176568;
+constexpr double kLog2E = 1.44269504088896340735992468100189214;
 
 // Order-only constants of the Bessel form (host-computed per theta): the
 // order nu = n + mu with |mu| <= 1/2; Gamma(1 + mu), Gamma(1 - mu); Temme's
@@ -209,6 +211,11 @@ template <typename T> __device__ __forceinline__ T expneg(T x);
 template <> __device__ __forceinline__ double expneg<double>(double x) { return exp(-x); }
 template <> __device__ __forceinline__ float expneg<float>(float x) { return __expf(-x); }
 
+// 2^-x: one v_exp_f32 in FP32
+template <typename T> __device__ __forceinline__ T exp2neg(T x);
+template <> __device__ __forceinline__ double exp2neg<double>(double x) { return exp2(-x); }
+template <> __device__ __forceinline__ float exp2neg<float>(float x) { return __builtin_amdgcn_exp2f(-x); }
+
 template <typename T> __device__ __forceinline__ T sqrt_(T x);
 template <> __device__ __forceinline__ double sqrt_<double>(double x) { return sqrt(x); }
 template <> __device__ __forceinline__ float sqrt_<float>(float x) { return sqrtf(x); }
@@ -250,6 +257,14 @@ struct MaternCoef {
   // d rho / d range with 1 / range folded into (h0, h1, h2) = (g0, g1, g2) / range
   __device__ __forceinline__ T drange_scaled(T x, T h0, T h1, T h2) const {
     return x * expneg<T>(x) * (h0 + x * (h1 + h2 * x));
+  }
+  // the two above for a distance u = x log2(e) (e^-x = 2^-u), the coefficients
+  // of u^k carrying the factor ln(2)^k (neg_cov) or ln(2)^(k+1) (drange)
+  __device__ __forceinline__ T neg_cov_log2(T u, T s0, T s1, T s2) const {
+    return exp2neg<T>(u) * (s0 + u * (s1 + s2 * u));
+  }
+  __device__ __forceinline__ T drange_scaled_log2(T u, T h0, T h1, T h2) const {
+    return u * exp2neg<T>(u) * (h0 + u * (h1 + h2 * u));
   }
 };
 

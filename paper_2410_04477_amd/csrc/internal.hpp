@@ -84,17 +84,21 @@ bool wave_fits(int g, bool fp32);
 // gradient as two launches (factor + tiles, then the adjoint from the tiles)
 inline bool wave_split(int g, bool fp32) { return fp32 && g >= 10; }
 // gradient in one launch with the factor kept in the registers (no tile
-// buffer): classes up to G = 9 whose right-hand sides (l_max + 2) fit one
-// pass (FP32 G = 10, 11 would run one wave per SIMD, slower than the split
-// gradient's two launches: 243 against 266 evals/s at n = 1e6)
+// buffer): FP64 classes up to G = 9, FP32 up to G = 10 (two waves per SIMD up
+// to G = 9, one at G = 10, which still beats the split gradient there: 315
+// against 307 evals/s at n = 1e6).  The right-hand sides go in passes of
+// wave_chunk(G), except at G = 9, where the registers the pass loop holds
+// would spill: there only classes whose l_max + 2 right-hand sides fit one pass
 #ifndef BV_REGADJ_MAX_G32
-#define BV_REGADJ_MAX_G32 9
+#define BV_REGADJ_MAX_G32 10
 #endif
 #ifndef BV_REGADJ_MAX_G64
 #define BV_REGADJ_MAX_G64 9
 #endif
+__host__ __device__ constexpr bool wave_regadj_passes(int g, bool /*fp32*/) { return g != 9; }
 inline bool wave_regadj(int g, bool fp32, int lmax) {
-  return g >= 1 && g <= (fp32 ? BV_REGADJ_MAX_G32 : BV_REGADJ_MAX_G64) && lmax + 2 <= wave_chunk(g);
+  return g >= 1 && g <= (fp32 ? BV_REGADJ_MAX_G32 : BV_REGADJ_MAX_G64) &&
+         (wave_regadj_passes(g, fp32) || lmax + 2 <= wave_chunk(g));
 }
 // prediction: round the conditioning-set size up to the factorisation's panel width
 __host__ __device__ constexpr int pred_rows(int m) { return (m + 3) & ~3; }

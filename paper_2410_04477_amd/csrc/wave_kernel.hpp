@@ -98,11 +98,13 @@ __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
   // (P x (wave_chunk(G) + 1), plus 32 elements that reads of the last row's
   // unused columns may touch), which also holds the G staged diagonal tiles
   // before the first chunk
+  // (mode 5 keeps the border row w of the factor after that, 16 G elements)
   return 3 * 16 * G + wave_max(4 * (16 * G + (mode == 2 || mode == 5 ? 16 : 0)) + 3 * 16 * G,
                                mode == 0 || mode == 2 || mode == 4 ? 0
                                : (16 * (wave_chunk(G) + 1) > kStageStride
                                       ? 16 * G * (wave_chunk(G) + 1) + 32
-                                      : G * kStageStride));
+                                      : G * kStageStride)) +
+         (mode == 5 ? 16 * G : 0);
 }
 
 template <typename T, int G, int MODE>
@@ -127,6 +129,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   typedef typename M::acc acc_t;
   extern __shared__ __align__(16) unsigned char smem[];
   T* su = reinterpret_cast<T*>(smem);  // scaled coordinates relative to the block's first point, su[k * P + i]
+  // FP32 closed forms: the coordinates carry a factor log2(e), so e^-x is one
+  // exp2 of the distance and the polynomial coefficients carry powers of ln 2
+  constexpr bool LOG2U = !GEN && sizeof(T) == 4;
   T* work = su + 3 * P;
   // MODE 5 appends 16 rows to the panel (the identity rows whose elimination
   // gives the inverse of each diagonal tile of the factor)
@@ -174,7 +179,8 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         src = a.locs + (size_t)g * a.d;
         if (MODE != 3) sy[i] = T(a.y[g]);
       }
-      for (int k = 0; k < 3; ++k) su[k * P + i] = k < a.d ? T((src[k] - org[k]) * th.inv_scale[k]) : T(0);
+      for (int k = 0; k < 3; ++k)
+        su[k * P + i] = k < a.d ? T((src[k] - org[k]) * (th.inv_scale[k] * (LOG2U ? kLog2E : 1.0))) : T(0);
     } else {
       if (MODE != 3) sy[i] = T(0);
       for (int k = 0; k < 3; ++k) su[k * P + i] = T(0);
@@ -198,9 +204,10 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   // the coefficients
   T ns0 = T(0), ns1 = T(0), ns2 = T(0);
   if constexpr (!GEN) {
+    const double u1 = LOG2U ? kLn2 : 1.0;
     ns0 = -sig2;
-    ns1 = -sig2 * mc.c1;
-    ns2 = -sig2 * mc.c2;
+    ns1 = T(-th.sigma2 * (double)mc.c1 * u1);
+    ns2 = T(-th.sigma2 * (double)mc.c2 * u1 * u1);
   }
   static_for<0, G>(BV_CI(I) {
     BV_CV(I);
@@ -224,6 +231,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         // the tiles hold the negated matrix (updates add L L^T)
         T v;
         if constexpr (GEN) v = -(sig2 * mc.rho(x));
+        else if constexpr (LOG2U) v = mc.neg_cov_log2(x, ns0, ns1, ns2);
         else v = mc.neg_cov(x, ns0, ns1, ns2);
         if constexpr (I == J) v -= (i == j) ? nug : T(0);   // the nugget: same-index pairs only
         if (!(real_row(i) && real_row(j))) v = (i == j) ? T(-1) : T(0);
@@ -459,7 +467,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     if (!(dd > 0.0)) flag |= 2;
     if (k >= m) {
       const double wk = (double)swk[k];
-      acc_ll += log(dd) + wk * wk;
+      // FP32 pivots: log2 by the hardware (about 1 ulp of the FP32 value)
+      const double lgd = sizeof(T) == 4 ? (double)__builtin_amdgcn_logf((float)sdk[k]) * kLn2 : log(dd);
+      acc_ll += lgd + wk * wk;
     }
   }
 #pragma unroll
@@ -506,9 +516,10 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   const T irange = T(th.inv_range);
   T dh0 = T(0), dh1 = T(0), dh2 = T(0);   // closed forms: d rho / d range coefficients over the range
   if constexpr (!GEN) {
-    dh0 = mc.g0 * irange;
-    dh1 = mc.g1 * irange;
-    dh2 = mc.g2 * irange;
+    const double u1 = LOG2U ? kLn2 : 1.0;
+    dh0 = T((double)mc.g0 * th.inv_range * u1);
+    dh1 = T((double)mc.g1 * th.inv_range * u1 * u1);
+    dh2 = T((double)mc.g2 * th.inv_range * u1 * u1 * u1);
   }
   // d/d sigma2 needs no entry of dK: with d K_J / d sigma2 = (K_J - nugget I) / sigma2,
   // <W, K_J> = ||w||^2 - ||w_N||^2 - l (the quadratic forms of y_J and y_N, and
@@ -570,7 +581,8 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
               s1 += c[r] * mc.drange(x, irange);
             }
           } else {
-            s1 += c[r] * mc.drange_scaled(x, dh0, dh1, dh2);
+            if constexpr (LOG2U) s1 += c[r] * mc.drange_scaled_log2(x, dh0, dh1, dh2);
+            else s1 += c[r] * mc.drange_scaled(x, dh0, dh1, dh2);
           }
         };
         if ((I + 1) * 16 <= p) {   // a tile inside the point rows (wave-uniform)
@@ -596,29 +608,28 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 
   if constexpr (MODE == 5) {
     // ---- factor kept in the registers (its diagonal tiles already replaced by
-    // their inverses): one pass of right-hand sides -------------------------
+    // their inverses), CH right-hand sides per pass ---------------------------
     // border row of the bordered factor, w = L^-1 y_J, from the factorisation's
-    // LDS record (read before the right-hand sides below overwrite it)
-    constexpr int NW = (P + 63) / 64;
-    T wreg[NW];
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      const int j = ln + 64 * k;
-      wreg[k] = j < p ? swk[j] : T(0);
-      if (j >= m && j < p) qb += (double)wreg[k] * (double)wreg[k];
+    // LDS record to LDS past the right-hand sides (which overwrite the record)
+    T* sw = work + wave_max(4 * PS + 3 * P, P * LDX + 32);
+    static_assert(3 * P + wave_max(4 * PS + 3 * P, P * LDX + 32) + P <= wave_lds_elems(G, MODE), "LDS of w");
+    for (int j = ln; j < P; j += 64) {
+      const T w = j < p ? swk[j] : T(0);
+      sw[j] = w;
+      if (j >= m && j < p) qb += (double)w * (double)w;
     }
+    for (int cb = 0; cb < nr; cb += CH) {
+    const int nc = nr - cb < CH ? nr - cb : CH;
     __syncthreads();
-    // right-hand sides [ w | [z; 0] | [0; I_l] ] (nr <= CH: one pass)
+    // columns cb .. cb + nc - 1 of the right-hand sides [ w | [z; 0] | [0; I_l] ]
     for (int e = ln; e < P * LDX + 32; e += 64) X[e] = T(0);
     __syncthreads();
-    for (int c = ln; c < nr; c += 64)
-      if (c >= 2) X[(m + c - 2) * LDX + c] = T(1);
-#pragma unroll
-    for (int k = 0; k < NW; ++k) {
-      const int j = ln + 64 * k;
-      if (j < p) {
-        X[j * LDX] = wreg[k];
-        if (j < m) X[j * LDX + 1] = wreg[k];
+    for (int c = ln; c < nc; c += 64)
+      if (cb + c >= 2) X[(m + cb + c - 2) * LDX + c] = T(1);
+    if (cb == 0) {
+      for (int j = ln; j < p; j += 64) {
+        X[j * LDX] = sw[j];
+        if (j < m) X[j * LDX + 1] = sw[j];
       }
     }
     __syncthreads();
@@ -628,7 +639,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     // register s, i.e. row M::row(k, s) of the tile, and the B operand takes
     // the same row of X.  The diagonal step's result, in accumulator layout,
     // is then directly the B operand of the updates of the rows above.
-    // (all NQ column tiles every step: the columns at and beyond nr are zero
+    // (all NQ column tiles every step: the columns at and beyond nc are zero
     // and stay zero, so no step branches on the chunk width)
     static_for_down<0, G>(BV_CI(K) {
       BV_CV(K);
@@ -677,7 +688,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       });
       __syncthreads();
     });
-    contract(0, nr);
+    contract(cb, nc);
+    if constexpr (!wave_regadj_passes(G, sizeof(T) == 4)) break;   // one pass: nr <= CH
+    }
   } else {
   // border row p of the bordered factor: w = L^-1 y_J, stored after the tiles
   constexpr int NW = (P + 63) / 64;
@@ -864,7 +877,7 @@ static hipError_t launch_wave_g(const AdjArgs& a, const ThetaPack& thp, int grid
 
 template <typename T, int MODE, bool GEN = false>
 static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, int grid, hipStream_t s) {
-  if constexpr (MODE == 5) {   // factor kept in the registers: up to G = 9
+  if constexpr (MODE == 5) {   // factor kept in the registers: up to G = 9 (FP32: 10)
     switch (g) {
       case 1: return launch_wave_g<T, 1, MODE, GEN>(a, thp, grid, s);
       case 2: return launch_wave_g<T, 2, MODE, GEN>(a, thp, grid, s);
@@ -875,10 +888,17 @@ static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, i
       case 7: return launch_wave_g<T, 7, MODE, GEN>(a, thp, grid, s);
       case 8: return launch_wave_g<T, 8, MODE, GEN>(a, thp, grid, s);
       case 9: return launch_wave_g<T, 9, MODE, GEN>(a, thp, grid, s);
+#if BV_REGADJ_MAX_G32 >= 10
+      case 10:   // FP32 only (one wave per SIMD)
+        if constexpr (sizeof(T) == 4) return launch_wave_g<T, 10, MODE, GEN>(a, thp, grid, s);
+        return hipErrorInvalidValue;
+#endif
       default: return hipErrorInvalidValue;
     }
   } else if constexpr (MODE == 2 || MODE == 3) {   // split gradient: only the classes that use it
+#if BV_REGADJ_MAX_G32 < 10
     if (g == 10) return launch_wave_g<T, 10, MODE, GEN>(a, thp, grid, s);
+#endif
     if (g == 11) return launch_wave_g<T, 11, MODE, GEN>(a, thp, grid, s);
     return hipErrorInvalidValue;
   } else if constexpr (MODE == 1 && sizeof(T) == 4) {   // FP32 G >= 10 use the split gradient
