@@ -245,7 +245,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       }
       // D = 0 * 0 + C: hands the finished tile to the accumulator registers now,
       // so the generated values do not pile up in VGPRs until the first update
-      acc[tix(I, J)] = M::op(T(0), T(0), acc[tix(I, J)]);
+      // (the FP32 gradient kernels up to G = 9 keep the tiles in VGPRs and skip it)
+      if constexpr (!(sizeof(T) == 4 && G <= 9 && (MODE == 5 || MODE == 2)))
+        acc[tix(I, J)] = M::op(T(0), T(0), acc[tix(I, J)]);
     });
   });
 
@@ -373,40 +375,97 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       for (int r = 0; r < 4; ++r)
         einv[r] = M::row(lg, r) == lr ? (K * 16 + lr < kend ? T(-1) : T(1)) : T(0);
     }
+    if constexpr (sizeof(T) == 4 && (MODE == 5 || MODE == 2)) {
+      // FP32 gradient, one step per panel of four columns: the rank-4 update of tile
+      // column K first (the next panel's columns are in it) and the finished
+      // columns kept, then the next panel is published before the update of
+      // the tiles right of column K is issued, and its factorisation follows
+      // while the matrix core still works on that update.  (FP64 keeps the
+      // plain order: its tiles leave no registers for the longer-lived panel;
+      // the value and prediction kernels measured faster in it as well.)
+      publish(std::integral_constant<int, K>{}, 0);
+      __syncthreads();
+      factor_panel(K * 16);
+      __syncthreads();
 #pragma nounroll
-    for (int c0 = 0; c0 < 16; c0 += 4) {
-      const int k0 = K * 16 + c0;
-      if (k0 >= kend) break;
-      publish(std::integral_constant<int, K>{}, c0);
-      __syncthreads();
-      factor_panel(k0);
-      __syncthreads();
-      T v[G];
-      static_for<K, G>(BV_CI(I) {
-        BV_CV(I);
-        v[I] = pan[lg * PS + I * 16 + lr];
-      });
-      static_for<K, G>(BV_CI(I) {
-        BV_CV(I);
-        static_for<K, I + 1>(BV_CI(J) {
-          BV_CV(J);
-          acc[tix(I, J)] = M::op(v[I], v[J], acc[tix(I, J)]);
-        });
-      });
-      if (EINV) einv = M::op(pan[lg * PS + P + lr], v[K], einv);
-      if (MODE != 0 && MODE != 4 && lr >= c0 && lr < c0 + 4) {
-        // keep the finished factor columns in the tiles
+      for (int c0 = 0;; c0 += 4) {
+        T v[G];
         static_for<K, G>(BV_CI(I) {
           BV_CV(I);
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[tix(I, K)][r] = pan[(lr - c0) * PS + I * 16 + M::row(lg, r)];
+          v[I] = pan[lg * PS + I * 16 + lr];
         });
-        if (EINV) {
+        static_for<K, G>(BV_CI(I) {
+          BV_CV(I);
+          acc[tix(I, K)] = M::op(v[I], v[K], acc[tix(I, K)]);
+        });
+        if (EINV) einv = M::op(pan[lg * PS + P + lr], v[K], einv);
+        if (MODE != 0 && MODE != 4 && lr >= c0 && lr < c0 + 4) {
+          // keep the finished factor columns in the tiles
+          static_for<K, G>(BV_CI(I) {
+            BV_CV(I);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) einv[r] = pan[(lr - c0) * PS + P + M::row(lg, r)];
+            for (int r = 0; r < 4; ++r) acc[tix(I, K)][r] = pan[(lr - c0) * PS + I * 16 + M::row(lg, r)];
+          });
+          if (EINV) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) einv[r] = pan[(lr - c0) * PS + P + M::row(lg, r)];
+          }
         }
+        // the rank-4 update of the tiles right of tile column K
+        auto trailing = [&]() __attribute__((always_inline)) {
+          static_for<K + 1, G>(BV_CI(I) {
+            BV_CV(I);
+            static_for<K + 1, I + 1>(BV_CI(J) {
+              BV_CV(J);
+              acc[tix(I, J)] = M::op(v[I], v[J], acc[tix(I, J)]);
+            });
+          });
+        };
+        const bool next = c0 + 4 < 16 && K * 16 + c0 + 4 < kend;
+        __syncthreads();
+        if (next) publish(std::integral_constant<int, K>{}, c0 + 4);
+        __syncthreads();
+        trailing();
+        if (!next) break;
+        factor_panel(K * 16 + c0 + 4);
+        __syncthreads();
       }
-      __syncthreads();
+    } else {
+#pragma nounroll
+      for (int c0 = 0; c0 < 16; c0 += 4) {
+        const int k0 = K * 16 + c0;
+        if (k0 >= kend) break;
+        publish(std::integral_constant<int, K>{}, c0);
+        __syncthreads();
+        factor_panel(k0);
+        __syncthreads();
+        T v[G];
+        static_for<K, G>(BV_CI(I) {
+          BV_CV(I);
+          v[I] = pan[lg * PS + I * 16 + lr];
+        });
+        static_for<K, G>(BV_CI(I) {
+          BV_CV(I);
+          static_for<K, I + 1>(BV_CI(J) {
+            BV_CV(J);
+            acc[tix(I, J)] = M::op(v[I], v[J], acc[tix(I, J)]);
+          });
+        });
+        if (EINV) einv = M::op(pan[lg * PS + P + lr], v[K], einv);
+        if (MODE != 0 && MODE != 4 && lr >= c0 && lr < c0 + 4) {
+          // keep the finished factor columns in the tiles
+          static_for<K, G>(BV_CI(I) {
+            BV_CV(I);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) acc[tix(I, K)][r] = pan[(lr - c0) * PS + I * 16 + M::row(lg, r)];
+          });
+          if (EINV) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) einv[r] = pan[(lr - c0) * PS + P + M::row(lg, r)];
+          }
+        }
+        __syncthreads();
+      }
     }
     if constexpr (EINV) {
       // inv(L_KK) = (L_KK^-T)^T into the diagonal tile, transposed through LDS
