@@ -90,6 +90,17 @@ constexpr int kStageStride = 260;   // staged 16 x 16 tiles, padded so tiles fou
 
 __host__ __device__ constexpr int wave_max(int x, int y) { return x > y ? x : y; }
 
+// The kernels below run one wave per workgroup, and a wave's LDS operations
+// are performed in issue order, so lanes exchange data through LDS with a
+// wavefront-scope fence (it keeps the compiler from moving LDS accesses across
+// it) and no wait for the LDS traffic.  Exchanges through global memory (the
+// tile buffer of mode 1) keep the workgroup barrier.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
   // su (3 P) for the whole kernel, then a work region: the panel (4 columns of
   // P rows, plus 16 appended rows in the modes that form the diagonal inverses
@@ -186,7 +197,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       for (int k = 0; k < 3; ++k) su[k * P + i] = T(0);
     }
   }
-  __syncthreads();
+  wave_lds_sync();
   const size_t o = (size_t)tt * a.bc + b;
   // tile slot (MODE 1-3): the NT factor tiles (MODE 2: the diagonal ones
   // replaced by their inverses), then the border row w (16 G elements)
@@ -384,9 +395,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
       // plain order: its tiles leave no registers for the longer-lived panel;
       // the value and prediction kernels measured faster in it as well.)
       publish(std::integral_constant<int, K>{}, 0);
-      __syncthreads();
+      wave_lds_sync();
       factor_panel(K * 16);
-      __syncthreads();
+      wave_lds_sync();
 #pragma nounroll
       for (int c0 = 0;; c0 += 4) {
         T v[G];
@@ -422,13 +433,13 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
           });
         };
         const bool next = c0 + 4 < 16 && K * 16 + c0 + 4 < kend;
-        __syncthreads();
+        wave_lds_sync();
         if (next) publish(std::integral_constant<int, K>{}, c0 + 4);
-        __syncthreads();
+        wave_lds_sync();
         trailing();
         if (!next) break;
         factor_panel(K * 16 + c0 + 4);
-        __syncthreads();
+        wave_lds_sync();
       }
     } else {
 #pragma nounroll
@@ -436,9 +447,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         const int k0 = K * 16 + c0;
         if (k0 >= kend) break;
         publish(std::integral_constant<int, K>{}, c0);
-        __syncthreads();
+        wave_lds_sync();
         factor_panel(k0);
-        __syncthreads();
+        wave_lds_sync();
         T v[G];
         static_for<K, G>(BV_CI(I) {
           BV_CV(I);
@@ -464,17 +475,17 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
             for (int r = 0; r < 4; ++r) einv[r] = pan[(lr - c0) * PS + P + M::row(lg, r)];
           }
         }
-        __syncthreads();
+        wave_lds_sync();
       }
     }
     if constexpr (EINV) {
       // inv(L_KK) = (L_KK^-T)^T into the diagonal tile, transposed through LDS
 #pragma unroll
       for (int r = 0; r < 4; ++r) pan[lr * 16 + M::row(lg, r)] = einv[r];
-      __syncthreads();
+      wave_lds_sync();
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[tix(K, K)][r] = pan[M::row(lg, r) * 16 + lr];
-      __syncthreads();
+      wave_lds_sync();
     }
   });
 
@@ -679,10 +690,10 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     }
     for (int cb = 0; cb < nr; cb += CH) {
     const int nc = nr - cb < CH ? nr - cb : CH;
-    __syncthreads();
+    wave_lds_sync();
     // columns cb .. cb + nc - 1 of the right-hand sides [ w | [z; 0] | [0; I_l] ]
     for (int e = ln; e < P * LDX + 32; e += 64) X[e] = T(0);
-    __syncthreads();
+    wave_lds_sync();
     for (int c = ln; c < nc; c += 64)
       if (cb + c >= 2) X[(m + cb + c - 2) * LDX + c] = T(1);
     if (cb == 0) {
@@ -691,7 +702,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         if (j < m) X[j * LDX + 1] = sw[j];
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     // X <- L^-T X, tile row by tile row from the bottom.  Every product
     // contracts over the rows of a factor tile, so the accumulator registers
     // serve as the A operand as they are: k-step s of lane (i, k) takes
@@ -745,7 +756,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
             for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = cj[q][r];
           }
       });
-      __syncthreads();
+      wave_lds_sync();
     });
     contract(cb, nc);
     if constexpr (!wave_regadj_passes(G, sizeof(T) == 4)) break;   // one pass: nr <= CH
@@ -779,7 +790,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         X[K * kStageStride + rw * 16 + lr] = v;
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     const int c = lr;
     T x[NB][16];
     const T* Lk[NB];
@@ -816,9 +827,9 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   for (int cb = 0; cb < nr; cb += CH) {
     const int nc = nr - cb < CH ? nr - cb : CH;
     const int nq = (nc + 15) >> 4;
-    __syncthreads();
+    wave_lds_sync();
     for (int e = ln; e < P * LDX + 32; e += 64) X[e] = T(0);
-    __syncthreads();
+    wave_lds_sync();
     // column cb + c of [ w | [z; 0] | [0; I_l] ]
     for (int c = ln; c < nc; c += 64)
       if (cb + c >= 2) X[(m + cb + c - 2) * LDX + c] = T(1);
@@ -832,7 +843,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         }
       }
     }
-    __syncthreads();
+    wave_lds_sync();
     for (int K = Gp - 1; K >= 0; --K) {
       const T* Lrow = Lg + (K * (K + 1) / 2) * 256;   // tile row K: tiles (K, 0..K)
       // A operands from the tile buffer: inv(L_KK)^T and -L_KJ^T, J < K
@@ -857,14 +868,14 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
           for (int sb = 0; sb < 4; ++sb) dq[q] = M::op(ad[sb], X[(K * 16 + 4 * sb + lg) * LDX + q * 16 + lr], dq[q]);
         }
       }
-      __syncthreads();
+      wave_lds_sync();
 #pragma unroll
       for (int q = 0; q < 2; ++q)
         if (q < nq && colok(q)) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) X[(K * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = dq[q][r];
         }
-      __syncthreads();
+      wave_lds_sync();
       // rows above: X_J -= L_KJ^T X_K (all tiles loaded first, then the MFMA chains)
       if (K > 0) {
         T bq[2][4];
@@ -900,7 +911,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
                 for (int r = 0; r < 4; ++r) X[(J * 16 + M::row(lg, r)) * LDX + q * 16 + lr] = cj[J][q][r];
               }
           }
-        __syncthreads();
+        wave_lds_sync();
       }
     }
 
