@@ -351,6 +351,10 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 // value + gradient call: 0 value, 5 gradient with the factor in registers,
 // 1 gradient through the tile buffer, 23 the split gradient (mode 2 then 3);
 // -1 when the class does not run the one-wave kernels.
+#ifndef BV_MARK_SPLIT
+#define BV_MARK_SPLIT 1
+#endif
+constexpr bool kMarkSplit = BV_MARK_SPLIT;
 static int class_wave_mode(const vecchia_plan* plan, int q, bool fp32, bool with_grad) {
   const int g = plan->bucket_cfg[q] + 1;
   // (the FP64 one-wave kernels above G = 9 spill part of their tiles, yet at
@@ -861,7 +865,7 @@ static int loglik_grad_run(const vecchia_plan* plan, const double* locs_perm, co
     // (two-launch) class with the most blocks, so that the long one-wave-per-SIMD
     // factorisation items start first and the fine-grained class fills in last
     int qmark = -1;
-    if (conc && plan->engine == kEngineMfma)
+    if (conc && plan->engine == kEngineMfma && kMarkSplit)
       for (int q = 0; q < plan->nbuckets; ++q)
         if (q != plan->bucket_main && plan->bucket_cfg[q] != kLargeCfg && class_wave_mode(plan, q, fp32, true) == 23 &&
             (qmark < 0 || plan->bucket_off[q + 1] - plan->bucket_off[q] >

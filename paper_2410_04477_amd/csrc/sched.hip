@@ -74,13 +74,16 @@ __global__ void compact_flagged_kernel(const int* __restrict__ sched, int nsched
 }
 
 // Deterministic FP64 sum of per-block terms for one theta per workgroup:
-// thread j sums entries j, j+256, ... in order, then a fixed LDS tree.
+// thread j sums entries j, j+kRed, ... in order, then a fixed LDS tree
+// (kRed = 1024 threads: the loop is bound by load latency, so the more loads
+// in flight the better).
 // counters[2t] = blocks re-factorised in FP64, counters[2t+1] = non-PD blocks.
-__global__ void __launch_bounds__(256)
+constexpr int kRed = 1024;
+__global__ void __launch_bounds__(kRed)
 reduce_partials_kernel(const double* __restrict__ partial, const int* __restrict__ flag, int bc, int fp64_only,
                        double* __restrict__ out, int* __restrict__ counters) {
-  __shared__ double ssum[256];
-  __shared__ int sref[256], sbad[256];
+  __shared__ double ssum[kRed];
+  __shared__ int sref[kRed], sbad[kRed];
   const int tt = blockIdx.x;
   const double* pp = partial + (size_t)tt * bc;
   const int* ff = flag + (size_t)tt * bc;
@@ -88,7 +91,7 @@ reduce_partials_kernel(const double* __restrict__ partial, const int* __restrict
   int nref = 0, nbad = 0;
   // unrolled so that several loads are in flight; the additions keep their order
 #pragma unroll 8
-  for (int i = threadIdx.x; i < bc; i += 256) {
+  for (int i = threadIdx.x; i < bc; i += kRed) {
     acc += pp[i];
     const int f = ff[i];
     nref += (f & 4) ? 1 : 0;
@@ -98,7 +101,7 @@ reduce_partials_kernel(const double* __restrict__ partial, const int* __restrict
   sref[threadIdx.x] = nref;
   sbad[threadIdx.x] = nbad;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = kRed / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) {
       ssum[threadIdx.x] += ssum[threadIdx.x + s];
       sref[threadIdx.x] += sref[threadIdx.x + s];
@@ -116,18 +119,18 @@ reduce_partials_kernel(const double* __restrict__ partial, const int* __restrict
 }
 
 // Same tree for k-component per-block vectors (gradients): out[t*k + c].
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kRed)
 reduce_vec_kernel(const double* __restrict__ vec, int bc, int k, double* __restrict__ out) {
-  __shared__ double ssum[256];
+  __shared__ double ssum[kRed];
   const int tt = blockIdx.x / k;
   const int c = blockIdx.x - tt * k;
   const double* pp = vec + (size_t)tt * bc * k;
   double acc = 0.0;
 #pragma unroll 8
-  for (int i = threadIdx.x; i < bc; i += 256) acc += pp[(size_t)i * k + c];
+  for (int i = threadIdx.x; i < bc; i += kRed) acc += pp[(size_t)i * k + c];
   ssum[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
+  for (int s = kRed / 2; s > 0; s >>= 1) {
     if (threadIdx.x < s) ssum[threadIdx.x] += ssum[threadIdx.x + s];
     __syncthreads();
   }
@@ -175,13 +178,13 @@ hipError_t launch_compact_flagged(const int* sched, int nsched, int ntheta, int 
 
 hipError_t launch_reduce_partials(const double* partial, const int* flag, int bc, int ntheta, int fp64_only,
                                   double* out, int* counters, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_partials_kernel, dim3(ntheta), dim3(256), 0, s, partial, flag, bc, fp64_only, out,
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(ntheta), dim3(kRed), 0, s, partial, flag, bc, fp64_only, out,
                      counters);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_vec(const double* vec, int bc, int k, int ntheta, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(reduce_vec_kernel, dim3(ntheta * k), dim3(256), 0, s, vec, bc, k, out);
+  hipLaunchKernelGGL(reduce_vec_kernel, dim3(ntheta * k), dim3(kRed), 0, s, vec, bc, k, out);
   return hipGetLastError();
 }
 

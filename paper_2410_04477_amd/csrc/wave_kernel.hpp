@@ -582,6 +582,14 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   const int nr = l + 2;
   const int Gp = (p + 15) >> 4;
   T* X = work;   // X[row * LDX + col], one chunk of right-hand sides
+  // clears X (and the 32 elements after it) with 16-byte stores
+  auto zero_x = [&]() __attribute__((always_inline)) {
+    constexpr int V = 16 / (int)sizeof(T);
+    static_assert((P * LDX + 32) % V == 0 && (3 * P * sizeof(T)) % 16 == 0, "16-byte stores into X");
+    typedef T vec_t __attribute__((ext_vector_type(V)));
+    vec_t* xv = reinterpret_cast<vec_t*>(X);
+    for (int e = ln; e < (P * LDX + 32) / V; e += 64) xv[e] = vec_t(0);
+  };
 
   const T irange = T(th.inv_range);
   T dh0 = T(0), dh1 = T(0), dh2 = T(0);   // closed forms: d rho / d range coefficients over the range
@@ -692,7 +700,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     const int nc = nr - cb < CH ? nr - cb : CH;
     wave_lds_sync();
     // columns cb .. cb + nc - 1 of the right-hand sides [ w | [z; 0] | [0; I_l] ]
-    for (int e = ln; e < P * LDX + 32; e += 64) X[e] = T(0);
+    zero_x();
     wave_lds_sync();
     for (int c = ln; c < nc; c += 64)
       if (cb + c >= 2) X[(m + cb + c - 2) * LDX + c] = T(1);
@@ -828,7 +836,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     const int nc = nr - cb < CH ? nr - cb : CH;
     const int nq = (nc + 15) >> 4;
     wave_lds_sync();
-    for (int e = ln; e < P * LDX + 32; e += 64) X[e] = T(0);
+    zero_x();
     wave_lds_sync();
     // column cb + c of [ w | [z; 0] | [0; I_l] ]
     for (int c = ln; c < nc; c += 64)
