@@ -351,6 +351,9 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 // value + gradient call: 0 value, 5 gradient with the factor in registers,
 // 1 gradient through the tile buffer, 23 the split gradient (mode 2 then 3);
 // -1 when the class does not run the one-wave kernels.
+// whether the largest class waits for the first factorisation half of the
+// split class (one wave per SIMD) before it starts; a build switch, measured
+// neutral since FP32 G = 10 moved to the register-resident kernel
 #ifndef BV_MARK_SPLIT
 #define BV_MARK_SPLIT 1
 #endif

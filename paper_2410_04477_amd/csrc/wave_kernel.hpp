@@ -14,18 +14,22 @@
 // redundancy costs nothing); each lane solves up to ceil((P - 16 K) / 64)
 // panel rows (the TRSM / TRSV of Alg. 1; the border row becomes
 // w = L^-1 y_J); the trailing tiles take one rank-4 MFMA each (the Schur
-// update).  Workgroup barriers of a single wave reduce to LDS fences, so a
-// panel costs no cross-wave synchronisation.  Pivots d_k and border entries
-// w_k (k >= m) give log det and the quadratic form, summed in FP64.
+// update).  Lanes exchange panel data through LDS with wavefront-scope
+// fences, so a panel costs no cross-wave synchronisation.  Pivots d_k and
+// border entries w_k (k >= m) give log det and the quadratic form, summed in
+// FP64.
 //
-// Adjoint (MODE 1): the factor tiles go to the item's slot of a global tile
-// buffer and leave the registers.  The diagonal 16 x 16 blocks of L are
-// inverted (16 lanes per block, all blocks in one pass) and written back, so
-// that X = L^-T [ w | [z; 0] | [0; I_l] ] is pure MFMA work tile row by tile
-// row: X_K <- inv(L_KK)^T X_K, then X_J -= L_KJ^T X_K for the rows above, with
-// the A operands read straight from the buffer.  W = alpha alpha^T - b b^T -
-// X_R X_R^T is formed tile by tile with MFMA and contracted against dK
-// regenerated entry by entry (FP64 across tiles): d l_i = 1/2 <W, dK>.
+// Adjoint: X = L^-T [ w | [z; 0] | [0; I_l] ] is pure MFMA work tile row by
+// tile row, X_K <- inv(L_KK)^T X_K, then X_J -= L_KJ^T X_K for the rows above;
+// W = alpha alpha^T - b b^T - X_R X_R^T is formed tile by tile with MFMA and
+// contracted against dK regenerated entry by entry (FP64 across tiles):
+// d l_i = 1/2 <W, dK>.  MODE 5 keeps the factor in the registers (the
+// diagonal inverses formed during the factorisation from 16 rows appended to
+// each panel) and takes its A operands from the accumulator registers;
+// MODE 1 stores the factor tiles to the item's slot of a global tile buffer,
+// inverts the diagonal blocks there (16 lanes per block, all blocks in one
+// pass) and reads its A operands from the buffer; MODES 2 + 3 split the two
+// halves over two launches.
 #pragma once
 
 #include <utility>
@@ -129,8 +133,8 @@ constexpr int wave_min_waves() { return sizeof(T) == 4 && (G <= 9 || MODE == 3) 
 // leaves the Schur complement -- the conditional covariance of the block and,
 // in the border row, minus its conditional mean -- in the trailing tiles.
 // 5 value and gradient in one launch with the factor kept in the registers
-// through the back-substitution (no tile buffer; one pass of right-hand sides,
-// l + 2 <= wave_chunk(G)).
+// through the back-substitution (no tile buffer; right-hand sides in passes
+// of wave_chunk(G), at G = 9 one pass only: l + 2 <= wave_chunk(G)).
 // GEN: covariances by the Bessel form for any nu instead of the closed forms.
 template <typename T, int G, int MODE, bool GEN>
 __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
