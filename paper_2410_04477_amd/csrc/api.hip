@@ -360,12 +360,14 @@ static AdjArgs as_adj(const FwdArgs& f, const vecchia_plan* plan) {
 constexpr bool kMarkSplit = BV_MARK_SPLIT;
 static int class_wave_mode(const vecchia_plan* plan, int q, bool fp32, bool with_grad) {
   const int g = plan->bucket_cfg[q] + 1;
-  // (the FP64 one-wave kernels above G = 9 spill part of their tiles, yet at
-  // n = 1e6 they run 84 evals/s of value + gradient against 55 for the
-  // four-wave kernels, whose tiles fit)
+  // (the FP64 one-wave value kernels above G = 9 spill part of their tiles,
+  // yet at n = 1e6 they run faster than the four-wave kernels, whose tiles fit;
+  // the FP64 gradient there factors left-looking, mode 6, and takes the
+  // adjoint from the stored tiles)
   if (plan->engine != kEngineMfma || plan->bucket_cfg[q] == kLargeCfg || !wave_fits(g, fp32)) return -1;
   if (!with_grad) return 0;
   if (wave_regadj(g, fp32, plan->bucket_lmax[q])) return 5;
+  if (wave_left(g, fp32)) return 63;
   return wave_split(g, fp32) ? 23 : 1;
 }
 
@@ -379,8 +381,8 @@ extern "C" int vecchia_plan_class_kernel(const vecchia_plan* plan, int32_t q, in
   int n;
   if (plan->bucket_cfg[q] == kLargeCfg)
     n = snprintf(name, (size_t)cap, "bv_large_kernel<%s>", t);
-  else if (mode == 23)
-    n = snprintf(name, (size_t)cap, "bv_wave_kernel<%s,%d,2>+bv_wave_kernel<%s,%d,3>", t, g, t, g);
+  else if (mode == 23 || mode == 63)
+    n = snprintf(name, (size_t)cap, "bv_wave_kernel<%s,%d,%d>+bv_wave_kernel<%s,%d,3>", t, g, mode / 10, t, g);
   else if (mode >= 0)
     n = snprintf(name, (size_t)cap, "bv_wave_kernel<%s,%d,%d>", t, g, mode);
   else if (plan->engine == kEngineTiles)
@@ -411,7 +413,12 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
     const size_t cap = tile_bytes / per;
     if (cap == 0) return VECCHIA_ENOMEM;
     const int chunk = cap < (size_t)grid ? (int)cap : grid;
-    if (s2 && wave_split(g, fp32) && chunk == grid && grid >= 2) {
+    // two launches: the factorisation + tile store (mode 2, or mode 6 for the
+    // FP64 left-looking one; its Bessel-form variant is not built: mode 1
+    // there), then the adjoint (mode 3)
+    const bool two = wmode == 23 || (wmode == 63 && !a.gen);
+    const int fm = wmode == 63 ? 6 : 2;
+    if (s2 && two && chunk == grid && grid >= 2) {
       // the split gradient in two halves on two streams: the adjoint launch of
       // one half overlaps the factorisation launch of the other, each half
       // with its own part of the tile buffer
@@ -422,7 +429,7 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
         a.tiles = static_cast<char*>(tiles) + (size_t)k * h * per;
         const int n = grid - k * h < h ? grid - k * h : h;
         const hipStream_t sk = (k & 1) ? s2 : s;
-        VCHECK_HIP(launch_wave(g, fp32, 2, a, thp, n, sk));
+        VCHECK_HIP(launch_wave(g, fp32, fm, a, thp, n, sk));
         if (k == 0 && mark) VCHECK_HIP(hipEventRecord(mark, sk));
         VCHECK_HIP(launch_wave(g, fp32, 3, a, thp, n, sk));
       }
@@ -432,8 +439,8 @@ static int launch_mfma_class(const vecchia_plan* plan, int q, bool fp32, int mod
     for (int w0 = 0; w0 < grid; w0 += chunk) {
       a.item_base = w0;
       const int n = grid - w0 < chunk ? grid - w0 : chunk;
-      if (wave_split(g, fp32)) {
-        VCHECK_HIP(launch_wave(g, fp32, 2, a, thp, n, s));
+      if (two) {
+        VCHECK_HIP(launch_wave(g, fp32, fm, a, thp, n, s));
         VCHECK_HIP(launch_wave(g, fp32, 3, a, thp, n, s));
       } else {
         VCHECK_HIP(launch_wave(g, fp32, 1, a, thp, n, s));

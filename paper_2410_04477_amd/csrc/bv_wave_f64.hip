@@ -8,6 +8,8 @@ hipError_t launch_wave_f64(int g, int mode, const AdjArgs& a, const ThetaPack& t
   if (mode == 1) return launch_wave_t<double, 1>(g, a, thp, grid, s);
   if (mode == 5) return launch_wave_t<double, 5>(g, a, thp, grid, s);
   if (mode == 4) return launch_wave_t<double, 4>(g, a, thp, grid, s);
+  if (mode == 6) return launch_wave_t<double, 6>(g, a, thp, grid, s);
+  if (mode == 3) return launch_wave_t<double, 3>(g, a, thp, grid, s);
   return hipErrorInvalidValue;
 }
 

@@ -83,6 +83,9 @@ constexpr size_t kAdjTileCap = (size_t)4 << 30;
 bool wave_fits(int g, bool fp32);
 // gradient as two launches (factor + tiles, then the adjoint from the tiles)
 inline bool wave_split(int g, bool fp32) { return fp32 && g >= 10; }
+// FP64 classes above G = 9: the factor + tiles launch left-looking by tile
+// columns (one tile column in the registers at a time), then the adjoint launch
+inline bool wave_left(int g, bool fp32) { return !fp32 && g >= 10; }
 // gradient in one launch with the factor kept in the registers (no tile
 // buffer): FP64 classes up to G = 9, FP32 up to G = 10 (two waves per SIMD up
 // to G = 9, one at G = 10, which still beats the split gradient there: 315

@@ -114,8 +114,8 @@ __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
   // unused columns may touch), which also holds the G staged diagonal tiles
   // before the first chunk
   // (mode 5 keeps the border row w of the factor after that, 16 G elements)
-  return 3 * 16 * G + wave_max(4 * (16 * G + (mode == 2 || mode == 5 ? 16 : 0)) + 3 * 16 * G,
-                               mode == 0 || mode == 2 || mode == 4 ? 0
+  return 3 * 16 * G + wave_max(4 * (16 * G + (mode == 2 || mode == 5 || mode == 6 ? 16 : 0)) + 3 * 16 * G,
+                               mode == 0 || mode == 2 || mode == 4 || mode == 6 ? 0
                                : (16 * (wave_chunk(G) + 1) > kStageStride
                                       ? 16 * G * (wave_chunk(G) + 1) + 32
                                       : G * kStageStride)) +
@@ -123,7 +123,7 @@ __host__ __device__ constexpr int wave_lds_elems(int G, int mode) {
 }
 
 template <typename T, int G, int MODE>
-constexpr int wave_min_waves() { return sizeof(T) == 4 && (G <= 9 || MODE == 3) ? 2 : 1; }
+constexpr int wave_min_waves() { return (sizeof(T) == 4 && (G <= 9 || MODE == 3)) || MODE == 6 ? 2 : 1; }
 
 // Modes: 0 value; 1 value and gradient in one launch; 2 value and the factor
 // tiles to the tile buffer; 3 gradient from those tiles (a second launch that
@@ -135,6 +135,12 @@ constexpr int wave_min_waves() { return sizeof(T) == 4 && (G <= 9 || MODE == 3) 
 // 5 value and gradient in one launch with the factor kept in the registers
 // through the back-substitution (no tile buffer; right-hand sides in passes
 // of wave_chunk(G), at G = 9 one pass only: l + 2 <= wave_chunk(G)).
+// 6 value and the factor tiles to the tile buffer, as mode 2, but left-looking
+// by tile columns: a tile column is generated when its turn comes, updated
+// with the stored columns to its left (MFMA, operands read back from the
+// buffer), factored in its four panels and stored, so that only one tile
+// column is in the registers at a time (FP64 classes above G = 9, whose tiles
+// exceed the register file); mode 3 takes the adjoint from its tiles.
 // GEN: covariances by the Bessel form for any nu instead of the closed forms.
 template <typename T, int G, int MODE, bool GEN>
 __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_kernel(AdjArgs a, ThetaPack thp) {
@@ -150,7 +156,8 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   T* work = su + 3 * P;
   // MODE 5 appends 16 rows to the panel (the identity rows whose elimination
   // gives the inverse of each diagonal tile of the factor)
-  constexpr bool EINV = MODE == 5 || MODE == 2;   // diagonal inverses formed during the factorisation
+  constexpr bool LEFT = MODE == 6;                // left-looking by tile columns
+  constexpr bool EINV = MODE == 5 || MODE == 2 || LEFT;   // diagonal inverses formed during the factorisation
   constexpr int PS = EINV ? P + 16 : P;            // panel column stride
   static_assert(3 * P + 4 * PS + 3 * P <= wave_lds_elems(G, MODE), "factorisation LDS");
   T* sy = work + 4 * PS;               // border row y_J
@@ -203,8 +210,8 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   }
   wave_lds_sync();
   const size_t o = (size_t)tt * a.bc + b;
-  // tile slot (MODE 1-3): the NT factor tiles (MODE 2: the diagonal ones
-  // replaced by their inverses), then the border row w (16 G elements)
+  // tile slot (MODE 1-3, 6): the NT factor tiles (MODES 2, 6: the diagonal
+  // ones replaced by their inverses), then the border row w (16 G elements)
   constexpr int SLOT = NT * 256 + 16 * G;
   T* Lg = reinterpret_cast<T*>(a.tiles) + (size_t)(wi - a.item_base) * SLOT;
   double acc_ll = 0.0;
@@ -224,6 +231,48 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     ns1 = T(-th.sigma2 * (double)mc.c1 * u1);
     ns2 = T(-th.sigma2 * (double)mc.c2 * u1 * u1);
   }
+  // mode 6: tile row I's coordinates (row M::row(lg, r) of the tile in ri[r])
+  // and the generation of one tile, as in the loop below
+  auto row_coords = [&](int I, T (&ri)[4][3]) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = I * 16 + M::row(lg, r);
+      ri[r][0] = su[i];
+      ri[r][1] = su[P + i];
+      ri[r][2] = su[2 * P + i];
+    }
+  };
+  auto gen_tile = [&](auto I_c, auto J_c, const T (&ri)[4][3]) __attribute__((always_inline)) {
+    constexpr int I = decltype(I_c)::value, J = decltype(J_c)::value;
+    const int j = J * 16 + lr;
+    const T sj0 = su[j], sj1 = su[P + j], sj2 = su[2 * P + j];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = I * 16 + M::row(lg, r);
+      const T dx = ri[r][0] - sj0, dy = ri[r][1] - sj1, dz = ri[r][2] - sj2;
+      const T x = sqrt_fast<T>(dx * dx + dy * dy + dz * dz);
+      // the tiles hold the negated matrix (updates add L L^T)
+      T v;
+      if constexpr (GEN) v = -(sig2 * mc.rho(x));
+      else if constexpr (LOG2U) v = mc.neg_cov_log2(x, ns0, ns1, ns2);
+      else v = mc.neg_cov(x, ns0, ns1, ns2);
+      if constexpr (I == J) v -= (i == j) ? nug : T(0);   // the nugget: same-index pairs only
+      if (!(real_row(i) && real_row(j))) v = (i == j) ? T(-1) : T(0);
+      acc[tix(I, J)][r] = v;
+    }
+    if (I == (p >> 4)) {  // border row p: y_J
+      const T yb = sy[j];
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (I * 16 + M::row(lg, r) == p && j < p) acc[tix(I, J)][r] = -yb;
+    }
+    // D = 0 * 0 + C: hands the finished tile to the accumulator registers now,
+    // so the generated values do not pile up in VGPRs until the first update
+    // (the FP32 gradient kernels up to G = 9 keep the tiles in VGPRs and skip it)
+    if constexpr (!(sizeof(T) == 4 && G <= 9 && (MODE == 5 || MODE == 2)))
+      acc[tix(I, J)] = M::op(T(0), T(0), acc[tix(I, J)]);
+  };
+  if constexpr (!LEFT) {   // the whole matrix now (mode 6: a tile column at a time, through gen_tile)
   static_for<0, G>(BV_CI(I) {
     BV_CV(I);
     T ri[4][3];
@@ -265,6 +314,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         acc[tix(I, J)] = M::op(T(0), T(0), acc[tix(I, J)]);
     });
   });
+  }
 
   // ---- factorisation, four columns per step -----------------------------------
   T* pan = work;  // pan[c * PS + row], c < 4
@@ -382,6 +432,33 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   static_for<0, G>(BV_CI(K) {
     BV_CV(K);
     if (K * 16 >= kend) return;
+    if constexpr (LEFT) {
+      // tile column K: generated now, then updated with the stored columns to
+      // its left, C_IK += L_IJ L_KJ^T (J < K, 16-wide contractions as four
+      // k-steps; both operands take element (lane % 16, 4 s + lane / 16) of
+      // their stored tile)
+      static_for<K, G>(BV_CI(I) {
+        BV_CV(I);
+        T ri[4][3];
+        row_coords(I, ri);
+        gen_tile(std::integral_constant<int, I>{}, std::integral_constant<int, K>{}, ri);
+      });
+      for (int Jp = 0; Jp < K; ++Jp) {
+        const T* LK = Lg + (size_t)(K * (K + 1) / 2 + Jp) * 256;
+        T bq[4];
+#pragma unroll
+        for (int sq = 0; sq < 4; ++sq) bq[sq] = LK[M::at(lr, 4 * sq + lg)];
+        static_for<K, G>(BV_CI(I) {
+          BV_CV(I);
+          const T* LI = Lg + (size_t)(I * (I + 1) / 2 + Jp) * 256;
+          T aq[4];
+#pragma unroll
+          for (int sq = 0; sq < 4; ++sq) aq[sq] = LI[M::at(lr, 4 * sq + lg)];
+#pragma unroll
+          for (int sq = 0; sq < 4; ++sq) acc[tix(I, K)] = M::op(aq[sq], bq[sq], acc[tix(I, K)]);
+        });
+      }
+    }
     if constexpr (EINV) {
       // -e_j for the columns the loop below eliminates; columns it skips (at
       // and beyond kend: the border column and the padding) keep +e_j, the
@@ -461,7 +538,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
         });
         static_for<K, G>(BV_CI(I) {
           BV_CV(I);
-          static_for<K, I + 1>(BV_CI(J) {
+          static_for<K, (LEFT ? K + 1 : I + 1)>(BV_CI(J) {   // mode 6: its own tile column only
             BV_CV(J);
             acc[tix(I, J)] = M::op(v[I], v[J], acc[tix(I, J)]);
           });
@@ -490,6 +567,16 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[tix(K, K)][r] = pan[M::row(lg, r) * 16 + lr];
       wave_lds_sync();
+    }
+    if constexpr (LEFT) {
+      // the finished tile column to the item's slot; the later columns read it
+      // back through global memory (hence the workgroup barrier)
+      static_for<K, G>(BV_CI(I) {
+        BV_CV(I);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) Lg[(I * (I + 1) / 2 + K) * 256 + ln * 4 + r] = acc[tix(I, K)][r];
+      });
+      __syncthreads();
     }
   });
 
@@ -551,7 +638,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     acc_ll += __shfl_down(acc_ll, off, 64);
     flag |= __shfl_down(flag, off, 64);
   }
-  if (MODE == 0 || MODE == 2) {
+  if (MODE == 0 || MODE == 2 || MODE == 6) {
     if (ln == 0) {
       a.partial[o] = (flag & 2) && !a.fp32_guard ? __builtin_nan("") : -0.5 * (acc_ll + (double)l * kLog2Pi);
       a.flag[o] = flag | a.flag_or;
@@ -562,16 +649,18 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
     // the factor leaves the registers for this item's slot of the tile buffer
     // (accumulator order, 256 elements per tile), so the adjoint's phases do not
     // hold the tiles in registers
-    static_for<0, NT>(BV_CI(t) {
-      BV_CV(t);
+    if constexpr (!LEFT) {   // (mode 6 stored its tiles column by column)
+      static_for<0, NT>(BV_CI(t) {
+        BV_CV(t);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Lg[t * 256 + ln * 4 + r] = acc[t][r];
-    });
-    // the border row w = L^-1 y_J (the diagonal tiles no longer hold it in MODE 2)
+        for (int r = 0; r < 4; ++r) Lg[t * 256 + ln * 4 + r] = acc[t][r];
+      });
+    }
+    // the border row w = L^-1 y_J (the diagonal tiles no longer hold it in MODES 2, 6)
     for (int j = ln; j < P; j += 64) Lg[NT * 256 + j] = j < p ? swk[j] : T(0);
     __syncthreads();
   }
-  if (MODE == 2) return;
+  if (MODE == 2 || MODE == 6) return;
   } else {
     flag = a.flag[o];   // written by the factorisation launch
   }
@@ -977,11 +1066,20 @@ static hipError_t launch_wave_t(int g, const AdjArgs& a, const ThetaPack& thp, i
 #endif
       default: return hipErrorInvalidValue;
     }
+  } else if constexpr (MODE == 6) {   // left-looking factorisation: FP64 above G = 9
+    if constexpr (sizeof(T) == 8) {
+      if (g == 10) return launch_wave_g<T, 10, MODE, GEN>(a, thp, grid, s);
+      if (g == 11) return launch_wave_g<T, 11, MODE, GEN>(a, thp, grid, s);
+    }
+    return hipErrorInvalidValue;
   } else if constexpr (MODE == 2 || MODE == 3) {   // split gradient: only the classes that use it
-#if BV_REGADJ_MAX_G32 < 10
-    if (g == 10) return launch_wave_g<T, 10, MODE, GEN>(a, thp, grid, s);
-#endif
-    if (g == 11) return launch_wave_g<T, 11, MODE, GEN>(a, thp, grid, s);
+    // (FP32: factorisation by mode 2; FP64: by mode 6, adjoint by mode 3 in both)
+    if constexpr (sizeof(T) == 4 || MODE == 3) {
+      if constexpr (sizeof(T) == 8 || BV_REGADJ_MAX_G32 < 10) {
+        if (g == 10) return launch_wave_g<T, 10, MODE, GEN>(a, thp, grid, s);
+      }
+      if (g == 11) return launch_wave_g<T, 11, MODE, GEN>(a, thp, grid, s);
+    }
     return hipErrorInvalidValue;
   } else if constexpr (MODE == 1 && sizeof(T) == 4) {   // FP32 G >= 10 use the split gradient
     switch (g) {

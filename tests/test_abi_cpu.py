@@ -74,6 +74,32 @@ def test_fp32_wave_kernels_keep_their_tiles_in_registers():
     assert seen == 32
 
 
+def test_fp64_gradient_kernels_do_not_spill():
+    """The FP64 closed-form gradient kernels the plans use keep their working
+    set in registers: the register-resident adjoint (mode 5, G <= 9), and for
+    the classes above G = 9 the left-looking factorisation (mode 6, one tile
+    column in the registers at a time, two waves per SIMD) and the adjoint from
+    the stored tiles (mode 3)."""
+    import json
+    import re
+    path = os.path.join(ROOT, "paper_2410_04477_amd", "_build", "kernel_resources.json")
+    if not os.path.exists(path):
+        pytest.skip("library not built")
+    res = json.load(open(path))
+    seen = {}
+    for name, r in res.items():
+        mt = re.search(r"bv_wave_kernelIdLi(\d+)ELi([356])ELb0E", name)
+        if not mt:
+            continue
+        g, mode = int(mt.group(1)), int(mt.group(2))
+        seen[(g, mode)] = r
+        assert r["scratch"] == 0, (name, r)
+        if mode == 6:
+            assert r["occupancy"] >= 2, (name, r)
+    assert {(g, 5) for g in range(1, 10)} <= set(seen)
+    assert {(10, 6), (11, 6), (10, 3), (11, 3)} <= set(seen)
+
+
 @pytest.mark.skipif(not os.path.exists(LIB), reason="library not built")
 def test_plan_layout_matches_binding_and_mismatch_is_caught():
     """The ctypes mirror of vecchia_plan must have the library's layout; a
