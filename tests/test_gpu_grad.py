@@ -82,11 +82,13 @@ def test_adjoint_many_right_hand_sides(bc, m, engine):
 
 
 def test_fp32_gradient_large_classes_vs_oracle():
-    """p_i + 1 in (144, 176]: the FP32 gradient of these size classes runs as two
-    launches (factorisation + tiles, then the adjoint from the tiles).  Per-block
-    FP32 terms within 1e-3 (norm-wise) of the FP64 oracle, FP32 values within
-    1e-3 per block and 1e-4 on the total; the forced-refactor path reproduces
-    FP64 exactly."""
+    """p_i + 1 in (144, 176]: the FP32 gradient of these size classes runs the
+    register-resident kernel at one wave per SIMD (G = 10) or two launches
+    (G = 11: factorisation + tiles, then the adjoint from the tiles); the FP64
+    one, direct or as the forced re-run of every block, the left-looking
+    factorisation launch and the adjoint launch.  Per-block FP32 terms within
+    1e-3 (norm-wise) of the FP64 oracle, FP32 values within 1e-3 per block and
+    1e-4 on the total; the forced-refactor path reproduces FP64 exactly."""
     th = W.Theta(1.0, 0.1, 2e-3, 1.5)
     pb = problem("big32", 3000, 2, 150, 130, th, 81)
     p = np.diff(pb["block_ptr"]) + np.diff(pb["nbr_ptr"])
