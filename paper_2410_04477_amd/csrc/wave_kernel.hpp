@@ -29,7 +29,8 @@
 // MODE 1 stores the factor tiles to the item's slot of a global tile buffer,
 // inverts the diagonal blocks there (16 lanes per block, all blocks in one
 // pass) and reads its A operands from the buffer; MODES 2 + 3 split the two
-// halves over two launches.
+// halves over two launches, and MODES 6 + 3 likewise with a left-looking
+// factorisation (FP64 above G = 9).
 #pragma once
 
 #include <utility>
@@ -98,7 +99,8 @@ __host__ __device__ constexpr int wave_max(int x, int y) { return x > y ? x : y;
 // are performed in issue order, so lanes exchange data through LDS with a
 // wavefront-scope fence (it keeps the compiler from moving LDS accesses across
 // it) and no wait for the LDS traffic.  Exchanges through global memory (the
-// tile buffer of mode 1) keep the workgroup barrier.
+// tile buffer of mode 1, the stored tile columns of mode 6) keep the workgroup
+// barrier.
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -218,7 +220,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
   int flag = 0;
   const MaternF<T, GEN> mc(th);
   acc_t acc[NT];   // the bordered matrix, then its factor (unused by MODE 3)
-  if constexpr (MODE != 3) {   // MODE 3 starts from the factor tiles of a MODE 2 launch
+  if constexpr (MODE != 3) {   // MODE 3 starts from the factor tiles of a MODE 2 or 6 launch
 
   // ---- generate the bordered joint matrix in the accumulator tiles ----------
   const T sig2 = T(th.sigma2), nug = T(th.nugget);
@@ -318,7 +320,7 @@ __global__ void __launch_bounds__(64, (wave_min_waves<T, G, MODE>())) bv_wave_ke
 
   // ---- factorisation, four columns per step -----------------------------------
   T* pan = work;  // pan[c * PS + row], c < 4
-  // MODES 5 and 2: the 16 rows appended below the matrix while tile column K is
+  // MODES 5, 2 and 6: the 16 rows appended below the matrix while tile column K is
   // eliminated, R = e_j^T at column 16 K + j (zero left of the tile column,
   // so earlier columns leave them untouched).  After the tile column they hold
   // R L_KK^-T = L_KK^-T, and the transpose of that, inv(L_KK), replaces L_KK
