@@ -182,9 +182,11 @@ int vecchia_reorder_blocks(const double* locs_perm, int64_t n, int32_t d, const 
  *   the factorisation) and the l_i + 2 right-hand sides run in passes of 28
  *   (32 at G = 10); at G = 9 only when they fit one pass.  Otherwise the
  *   factor goes to the auxiliary tile buffer (FP32 G = 11: a factorisation
- *   launch, then an adjoint launch) and the right-hand sides run in passes of
- *   up to 32, so any l_i fits the LDS.  FP64 classes above G = 9 exceed the
- *   register file and spill part of the tiles.
+ *   launch, then an adjoint launch; FP64 G = 10, 11: the same with a
+ *   left-looking factorisation that holds one tile column in the registers at
+ *   a time) and the right-hand sides run in passes of up to 32, so any l_i
+ *   fits the LDS.  The FP64 value kernels above G = 9 exceed the register
+ *   file and spill part of the tiles.
  * VECCHIA_ENGINE_MFMA_WG: the same tiles spread over the four waves of a
  *   workgroup, for every size class (two barriers per panel).
  * VECCHIA_ENGINE_TILES: one register tile per thread, one barrier per column
@@ -260,7 +262,8 @@ size_t vecchia_plan_workspace_size(int64_t bc, int32_t max_theta);
  * profiles and benchmark reports, e.g. "bv_wave_kernel<float,9,5>" (one-wave
  * kernel, FP32, G = 9 tile rows, mode 5: gradient with the factor kept in
  * registers; mode 1: through the tile buffer; "...,2>+...,3>": the split
- * gradient, factorisation then adjoint).  Host only.  VECCHIA_EINVAL for a bad
+ * gradient, factorisation then adjoint; "...,6>+...,3>": the same with the
+ * left-looking factorisation).  Host only.  VECCHIA_EINVAL for a bad
  * class index, VECCHIA_ENOMEM if cap bytes cannot hold the name. */
 int vecchia_plan_class_kernel(const vecchia_plan* plan, int32_t q, int32_t precision, int32_t with_grad,
                               char* name, int32_t cap);
