@@ -67,6 +67,36 @@ def span_roofline(kt, nclasses, flops, peak, kernel):
             "flops_per_launch": flops}
 
 
+def simulate_field(w, locs, locs_new, dev):
+    """y at the n observed locations (returned in their original order) and at
+    the held-out ones, by the sequential Vecchia simulator with w.sim_m
+    neighbours: the observed points in a seeded random order, then the
+    held-out points."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2410_04477_amd import api
+
+    th0 = w.theta
+    n_new = locs_new.shape[0]
+    order = W.point_permutation(w.n, w.seed_y)
+    inv_order = np.argsort(order)
+    metric = list(w.metric_scale)
+    locs_ord = torch.tensor(np.vstack([locs[order], locs_new]), device=dev)
+    unit = torch.arange(w.n + n_new + 1, dtype=torch.int32, device=dev)
+    log(f"simulating y: n={w.n} (+{n_new} held out), {w.sim_m} neighbours")
+    snptr, snidx = api.neighbors(locs_ord, unit, w.sim_m, metric)
+    z = torch.tensor(np.concatenate([W.standard_normal(w.n, w.seed_y), W.standard_normal(n_new, w.seed_y + 1)]),
+                     device=dev)
+    y_ord = api.simulate(locs_ord, snptr, snidx, (th0.sigma2, th0.beta, th0.nugget, th0.nu, th0.aniso), z)
+    y = api.permute_rows(y_ord[:w.n].contiguous(), torch.tensor(inv_order, device=dev))
+    y_new = y_ord[w.n:].contiguous()
+    torch.cuda.synchronize()
+    return y, y_new
+
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,20 +141,8 @@ def main() -> int:
     locs = W.locations(w)
     n_new = 0 if args.no_prediction else w.n // 10
     locs_new = W.new_locations(w, n_new)
-    order = W.point_permutation(w.n, w.seed_y)
-    inv_order = np.argsort(order)
     metric = list(w.metric_scale)
-    locs_ord = torch.tensor(np.vstack([locs[order], locs_new]), device=dev)
-    unit = torch.arange(w.n + n_new + 1, dtype=torch.int32, device=dev)
-    log(f"simulating y: n={w.n} (+{n_new} held out), {w.sim_m} neighbours")
-    snptr, snidx = api.neighbors(locs_ord, unit, w.sim_m, metric)
-    z = torch.tensor(np.concatenate([W.standard_normal(w.n, w.seed_y), W.standard_normal(n_new, w.seed_y + 1)]),
-                     device=dev)
-    y_ord = api.simulate(locs_ord, snptr, snidx, (th0.sigma2, th0.beta, th0.nugget, th0.nu, th0.aniso), z)
-    y = api.permute_rows(y_ord[:w.n].contiguous(), torch.tensor(inv_order, device=dev))
-    y_new = y_ord[w.n:].contiguous()
-    del snptr, snidx, locs_ord, unit, y_ord, z
-    torch.cuda.synchronize()
+    y, y_new = simulate_field(w, locs, locs_new, dev)
     t_sim = time.perf_counter() - t_setup
 
     # ---- preprocessing: K-means blocks, random order, neighbours, plan -------
@@ -282,6 +300,11 @@ def main() -> int:
     if n_new > 0:
         prediction = bench_prediction(model, locs_new, y_new, w, th0, metric, args.steps, dev)
 
+    # ---- blocks above the one-wave limit: the accuracy study's BV-1500-450 ----
+    large_blocks = None
+    if not args.no_prediction and args.scale == 1:
+        large_blocks = bench_large_blocks(W.C5, max(3, args.steps // 2), dev)
+
     # ---- block orderings (preprocessing, untimed in the step): Morton, Hilbert, KD-tree, maxmin --
     t_order = {}
     if not args.no_prediction:
@@ -326,6 +349,7 @@ def main() -> int:
         "accuracy": accuracy,
         "setup_s": {"simulate": t_sim, "preprocess": t_pre, **t_order},
         "prediction": prediction,
+        "large_blocks": large_blocks,
     }
     if args.copy_calibration:
         src = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
@@ -344,6 +368,71 @@ def pred_flops(m, l):
     the Schur update (m (l + 1)^2) and covariance generation (30 per entry)."""
     p = m + l
     return m ** 3 / 3.0 + m * m * (l + 1) + m * (l + 1) ** 2 + 30.0 * p * (p + 1) / 2.0
+
+
+def bench_large_blocks(w, steps, dev):
+    """Log-likelihood (value) on a workload whose blocks exceed the one-wave
+    limit (m_i + l_i > 175): the bordered matrix of each block is generated
+    into a workspace slot and factored left-looking in 16-column panels.
+    FP64 and FP32-bulk; the roofline is the large-block launch alone, from
+    the plan's own HIP events on the stream it runs on."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2410_04477_amd.model import BlockVecchia
+
+    th0 = w.theta
+    locs = W.locations(w)
+    y, _ = simulate_field(w, locs, np.zeros((0, w.d)), dev)
+    t0 = time.perf_counter()
+    model = BlockVecchia(locs, y, w.bc, w.m, th0.nu, W.kmeans_init(w.n, w.bc, w.seed_kmeans),
+                         W.block_permutation(w.bc, w.seed_kmeans), th0.aniso[: w.d], w.kmeans_iters)
+    torch.cuda.synchronize()
+    t_pre = time.perf_counter() - t0
+    plan = model.plan
+    classes = plan.buckets()
+    ql = [q for q in range(len(classes)) if plan.class_kernel(q, "fp64", False).startswith("bv_large_kernel")]
+    assert len(ql) == 1 and int(plan.c.nlarge) > 0, "the workload has no blocks above the one-wave limit"
+    ql = ql[0]
+    sched = plan.schedule().cpu().numpy()
+    bp = plan.block_ptr.cpu().numpy().astype(np.int64)
+    npt = plan.nbr_ptr.cpu().numpy().astype(np.int64)
+    psz = (np.diff(bp) + np.diff(npt)).astype(np.float64)
+    blk = sched[int(plan.c.bucket_off[ql]):int(plan.c.bucket_off[ql + 1])]
+    flops_large = float(np.sum(value_flops(psz[blk])))
+    thetas = [model.theta(t.sigma2, t.beta, t.nugget) for t in W.theta_cycle_c3(w)]
+    out = {"workload": f"{w.name}: n={w.n} 2-D uniform, nu={th0.nu}, sigma2={th0.sigma2}, beta={th0.beta}, "
+                       f"nugget={th0.nugget}, bc={w.bc}, m={w.m}, random block order, y by sequential "
+                       f"Vecchia ({w.sim_m} nbrs)",
+           "n": w.n, "bc": int(plan.bc), "m": w.m, "large_blocks": int(plan.c.nlarge),
+           "p_max": int(psz.max()), "p_mean_large": float(psz[blk].mean()), "preprocess_s": t_pre}
+    for prec in ("fp64", "fp32"):
+        for i in range(2):
+            model.loglik([thetas[i % len(thetas)]], prec)
+        torch.cuda.synchronize()
+        plan.set_timing(True)
+        plan.timing(reset=True)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            _, cnt = model.loglik([thetas[i % len(thetas)]], prec)[:2]
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / steps
+        kt = plan.timing(reset=True)
+        plan.set_timing(False)
+        k_s = kt[ql][0] / kt[ql][1] / 1e3
+        peak = FP64_PEAK if prec == "fp64" else FP32_PEAK
+        kname = plan.class_kernel(ql, prec, False)
+        out[prec] = {"loglik_evals_per_s": 1.0 / wall, "ms": wall * 1e3,
+                     "roofline": {"bound": "mfma", "achieved": flops_large / k_s / 1e12, "peak": peak / 1e12,
+                                  "unit": "TFLOP/s", "frac": flops_large / k_s / peak, "kernel": kname,
+                                  "avg_launch_ms": k_s * 1e3, "flops_per_launch": flops_large,
+                                  "share_of_step": k_s / wall},
+                     "blocks_refactored_fp64": int(cnt[0, 0]) if prec == "fp32" else 0}
+    l64 = float(model.loglik([thetas[0]], "fp64")[0][0])
+    l32 = float(model.loglik([thetas[0]], "fp32")[0][0])
+    out["rel_err_loglik_fp32_vs_fp64"] = abs(l32 - l64) / abs(l64)
+    return out
 
 
 def bench_prediction(model, locs_new, y_new, w, th0, metric, steps, dev):

@@ -109,3 +109,59 @@ def test_n1e6_3d_sampled_blocks_vs_oracle():
     assert abs(res["fp64"]["ll_v"] - res["fp64"]["ll"]) <= 1e-10 * abs(res["fp64"]["ll"])
     print(f"totals: fp64 {res['fp64']['ll']:.6f} fp32 {res['fp32']['ll']:.6f} "
           f"rel {abs(res['fp32']['ll'] - res['fp64']['ll']) / abs(res['fp64']['ll']):.1e}", flush=True)
+
+
+def test_n20k_m450_large_blocks_sampled_vs_oracle():
+    """The 20,000-point, 1,500-block, m = 450 workload at full size (every
+    block past the first few above the one-wave limit, so the large-block
+    kernel runs), in the plan configuration of the benchmark: per-block
+    log-likelihood terms, FP64 and FP32-bulk, on a seeded sample of 96 blocks
+    against the C oracle, with the sampled neighbour lists checked against
+    brute force first.  Oracle-side inputs as in the n = 1e6 case."""
+    from paper_2410_04477_amd import api
+    w = W.C5
+    th = w.theta
+    metric = list(w.metric_scale)
+    s = W.locations(w)
+    labels, _ = P.kmeans(s, metric, W.kmeans_init(w.n, w.bc, w.seed_kmeans), 3)
+    perm, bp = P.order_blocks(labels, W.block_permutation(w.bc, w.seed_kmeans))
+    lp = s[perm]
+    y = fourier_field(lp, th.sigma2, [th.beta * a for a in th.aniso], th.nugget, w.seed_y)
+    lp_t, y_t, bp_t = _t(lp), _t(y), _t(bp, torch.int32)
+    npt, nid = api.neighbors(lp_t, bp_t, w.m, metric)
+    plan = api.Plan(bp_t, npt, w.n, 1)
+    npt_h, nid_h = npt.cpu().numpy(), nid.cpu().numpy()
+    psz = np.diff(bp) + np.diff(npt_h)
+    print(f"n={w.n} bc={bp.size - 1} p {psz.min()}..{psz.max()}, {int(plan.c.nlarge)} large blocks", flush=True)
+    assert int(plan.c.nlarge) >= 0.95 * (bp.size - 1)
+    res = {}
+    for prec in ("fp64", "fp32"):
+        ll, cnt, part = api.loglik(plan, lp_t, y_t, nid, [th], prec, want_partial=True)
+        res[prec] = dict(ll=float(ll[0]), part=part[0].cpu().numpy(), cnt=cnt[0].cpu().numpy())
+
+    sample = np.sort(W.rng(2727).choice(bp.size - 1, size=96, replace=False))
+    x = lp * np.asarray(metric)
+    o_ptr = np.zeros(bp.size, dtype=np.int64)
+    rows = []
+    for i in sample:
+        a, b = int(bp[i]), int(bp[i + 1])
+        c = P.block_centroids(lp[a:b], np.array([0, b - a]), metric)[0]
+        ref = _knn_exact(c, x[:a], min(w.m, a)).astype(np.int64)
+        assert np.array_equal(nid_h[npt_h[i]:npt_h[i + 1]], ref), f"block {i}"
+        rows.append(ref)
+        o_ptr[i + 1] = ref.size
+    o_ptr = np.cumsum(o_ptr)
+    ref_l = coracle.selected_terms(lp, y, bp, o_ptr, np.concatenate(rows), th, sample, with_grad=False)
+    scale_l = np.abs(ref_l).mean()
+    for prec in ("fp64", "fp32"):
+        r = res[prec]
+        el = np.abs(r["part"][sample] - ref_l)
+        print(f"{prec}: max |dl_i| {el.max():.2e} (mean |l_i| {scale_l:.2e}), sum |dl_i| / sum |l_i| "
+              f"{el.sum() / np.abs(ref_l).sum():.1e}; guard re-factors {r['cnt'][0]}", flush=True)
+        if prec == "fp64":
+            assert el.max() <= 1e-8 * scale_l
+        else:
+            assert el.sum() <= 1e-4 * np.abs(ref_l).sum()
+        assert r["cnt"][1] == 0
+    assert abs(res["fp32"]["ll"] - res["fp64"]["ll"]) <= 1e-4 * abs(res["fp64"]["ll"])
+    print(f"totals: fp64 {res['fp64']['ll']:.6f} fp32 {res['fp32']['ll']:.6f}", flush=True)

@@ -72,7 +72,13 @@ C3 = Workload("n1M_3d_nu2.5_bc50k_m120", 1_000_000, 3,
 # Gradient / MLE workload: 200,000 points, nu=1.5.
 C4 = Workload("n200k_nu1.5_bc20k_m100", 200_000, 2, Theta(1.5, 0.08, 0.01, 1.5), 20_000, 100, 150, 4, 14, 24)
 
-WORKLOADS = {"C1": C1, "C2": C2, "C3": C3, "C4": C4}
+# Large conditioning sets: the accuracy study's BV-1500-450 setting (Section 3.1):
+# 20,000 points in the unit square, 1,500 blocks of about 13 points, 450
+# neighbours, nu = 1.5 at the middle effective range (0.3, beta = 0.052537).
+# m_i + l_i exceeds the one-wave limit of 175 for every block past the first few.
+C5 = Workload("n20k_nu1.5_bc1500_m450", 20_000, 2, Theta(1.0, 0.052537, 1e-4, 1.5), 1500, 450, 150, 5, 15, 25)
+
+WORKLOADS = {"C1": C1, "C2": C2, "C3": C3, "C4": C4, "C5": C5}
 
 # MLE start used with the gradient workload.
 C4_THETA0 = (1.0, 0.05, 0.05)
