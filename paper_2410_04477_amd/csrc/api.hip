@@ -253,8 +253,13 @@ extern "C" int vecchia_plan_init(vecchia_plan* plan, const int32_t* block_ptr, c
     ++nb;
     acc += hcounts[kLargeCfg];
     const int64_t work = plan->nlarge * (int64_t)max_theta;
-    plan->large_slots = (int32_t)(work < 256 ? work : 256);
     plan->large_slot_elems = (int64_t)large_slot_elems(hmax[0], hlmax[kLargeCfg]);
+    // one workgroup per slot: up to 8 per compute unit while the slots fit in
+    // kLargeSlotCap bytes, at least one per compute unit
+    const int64_t by_mem = (int64_t)(kLargeSlotCap / ((size_t)plan->large_slot_elems * sizeof(double)));
+    int64_t slots = by_mem < 2048 ? by_mem : 2048;
+    if (slots < 256) slots = 256;
+    plan->large_slots = (int32_t)(work < slots ? work : slots);
     plan->aux_ws_bytes = (size_t)plan->large_slots * (size_t)plan->large_slot_elems * sizeof(double);
   }
   if (engine == kEngineMfma && !predict) {

@@ -4,9 +4,11 @@
 // P = 16 G) is generated into a global workspace (column-major, lower part),
 // then factored left-looking in 16-column panels:
 //   C_IJ = A_IJ - sum_{K<J} L_IK L_JK^T      (MFMA, one output tile per wave at a time)
-//   L_JJ = chol(C_JJ), L_IJ = C_IJ L_JJ^-T  (one thread per row)
-// The log-determinant and quadratic form come from the panel pivots and the
-// border row, as in the register kernels.  Operands stream through L2: about
+//   L_JJ = chol(C_JJ)                        (one wave, rows in lane registers)
+//   L_IJ = C_IJ L_JJ^-T                      (one thread per row)
+// The matrix is generated with each thread owning a row and the columns staged
+// in LDS.  The log-determinant and quadratic form come from the panel pivots
+// and the border row, as in the register kernels.  Operands stream through L2: about
 // P^3 / 96 elements are read per block.  The gradient variant then
 // back-substitutes the right-hand sides [w | [w_N; 0] | [0; I_l]] through L^T
 // tile row by tile row (16 x 16 triangular solves, MFMA updates of the rows
@@ -45,15 +47,37 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Value of v held by lane `lane` (a compile-time or wave-uniform index).
+template <typename T> __device__ __forceinline__ T lane_read(T v, int lane);
+template <> __device__ __forceinline__ float lane_read<float>(float v, int lane) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), lane));
+}
+template <> __device__ __forceinline__ double lane_read<double>(double v, int lane) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+
 // Per-block slot layout (elements of T, P = 16 G for the block's own p):
 // the bordered matrix, column-major lower part, P x P; in gradient launches
 // the right-hand sides X (P rows, 16 ceil((l + 2) / 16) columns, column-major)
 // follow it; then the scaled coordinates of the p points (3 x P).
+// at least 6 waves per SIMD (80 VGPRs): 6 workgroups of 4 waves per compute
+// unit, so that up to 1536 blocks are in flight and hide each other's latency
+#ifndef BV_LARGE_WAVES
+#define BV_LARGE_WAVES 6
+#endif
+#ifndef BV_LARGE_UNROLL
+#define BV_LARGE_UNROLL 2   // panel-update steps whose operand loads are issued together
+#endif
+#define BV_PRAGMA(x) _Pragma(#x)
+#define BV_UNROLL(n) BV_PRAGMA(unroll n)
 template <typename T, bool GRAD>
-__global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack thp) {
+__global__ void __launch_bounds__(256, BV_LARGE_WAVES) bv_large_kernel(LargeArgs a, ThetaPack thp) {
   typedef typename LMma<T>::acc acc_t;
   __shared__ T dtile[16][17];
-  __shared__ T piv[16];
+  __shared__ T colc[4][256];   // generation: coordinates and y of 256 columns
   __shared__ double sred[2][256];
   const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63, lr = ln & 15, lg = ln >> 4;
   const int total = a.list ? *a.list_count : a.nsched * a.ntheta;
@@ -89,22 +113,42 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
                                           : T(0);
     }
     __syncthreads();
-    // ---- generate the lower part, column by column (rows over threads) -----
-    for (int j = 0; j < P; ++j) {
-      const int gj = j < m ? a.nbr_idx[n0 + j] : (b0 + j - m);
-      const T cj0 = cs[j], cj1 = cs[ld + j], cj2 = cs[2 * ld + j];
-      const T yj = j < p ? T(a.y[gj]) : T(0);
-      for (int i = j + tid; i < P; i += 256) {
-        T v;
-        if (i < p && j < p) {
-          const T d0 = cs[i] - cj0, d1 = cs[ld + i] - cj1, d2 = cs[2 * ld + i] - cj2;
-          v = sig2 * mc.rho(sqrt_<T>(d0 * d0 + d1 * d1 + d2 * d2)) + (i == j ? nug : T(0));
-        } else if (i == p && j < p) {
-          v = yj;
-        } else {
-          v = i == j ? T(1) : T(0);
+    // ---- generate the lower part: each thread owns a row (its coordinates in
+    // registers) and walks the columns, staged 256 at a time in LDS with their
+    // y values; for a fixed column the stores of a wave are contiguous -------
+    for (int ib = 0; ib < P; ib += 256) {
+      const int i = ib + tid;
+      const T ci0 = i < P ? cs[i] : T(0), ci1 = i < P ? cs[ld + i] : T(0), ci2 = i < P ? cs[2 * ld + i] : T(0);
+      for (int jb = 0; jb <= ib; jb += 256) {
+        __syncthreads();
+        {
+          const int j = jb + tid;
+          if (j < P) {
+            colc[0][tid] = cs[j];
+            colc[1][tid] = cs[ld + j];
+            colc[2][tid] = cs[2 * ld + j];
+            colc[3][tid] = j < p ? T(a.y[j < m ? a.nbr_idx[n0 + j] : (b0 + j - m)]) : T(0);
+          }
         }
-        M[(size_t)j * ld + i] = v;
+        __syncthreads();
+        const int jn = P - jb < 256 ? P - jb : 256;
+        if (i < P) {
+          for (int jj = 0; jj < jn; ++jj) {
+            const int j = jb + jj;
+            if (j <= i) {
+              T v;
+              if (i < p) {
+                const T d0 = ci0 - colc[0][jj], d1 = ci1 - colc[1][jj], d2 = ci2 - colc[2][jj];
+                v = sig2 * mc.rho(sqrt_<T>(d0 * d0 + d1 * d1 + d2 * d2)) + (i == j ? nug : T(0));
+              } else if (i == p && j < p) {
+                v = colc[3][jj];
+              } else {
+                v = i == j ? T(1) : T(0);
+              }
+              M[(size_t)j * ld + i] = v;
+            }
+          }
+        }
       }
     }
     __syncthreads();
@@ -113,6 +157,7 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
         : 0.0;
     double acc_ll = 0.0, qb = 0.0;
     int flag = 0;
+    T mypiv = T(1);
     const int Gp = (p + 15) >> 4;  // panels holding real columns
     for (int J = 0; J < Gp; ++J) {
       // panel update C_IJ = A_IJ - sum_{K<J} L_IK L_JK^T, output tiles I >= J dealt to waves
@@ -120,6 +165,7 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
         acc_t c;
 #pragma unroll
         for (int r = 0; r < 4; ++r) c[r] = M[(size_t)(J * 16 + lr) * ld + I * 16 + LMma<T>::row(lg, r)];
+        BV_UNROLL(BV_LARGE_UNROLL)
         for (int K = 0; K < J; ++K) {
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
@@ -134,31 +180,37 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
       }
       __threadfence_block();
       __syncthreads();
-      // diagonal tile: unblocked Cholesky by wave 0 in LDS
+      // diagonal tile: unblocked Cholesky by wave 0 in registers (lane r < 16
+      // holds row r; the entries of row k come by lane reads), then to LDS
       if (wv == 0) {
-        for (int e = ln; e < 256; e += 64) {
-          const int r = e & 15, c = e >> 4;
-          dtile[r][c] = M[(size_t)(J * 16 + c) * ld + J * 16 + r];
-        }
-      }
-      __syncthreads();
-      if (wv == 0) {
+        const int r = ln & 15;
+        T x[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) x[c] = M[(size_t)(J * 16 + c) * ld + J * 16 + r];
+#pragma unroll
         for (int k = 0; k < 16; ++k) {
-          const T dk = dtile[k][k];
+          const T dk = lane_read(x[k], k);
           const bool real = J * 16 + k < p;
           const T lkk = real ? sqrt_<T>(dk) : T(1);
-          if (ln == 0) piv[k] = real ? dk : T(1);
-          if (ln > k && ln < 16) dtile[ln][k] = real ? dtile[ln][k] / lkk : T(0);
-          wave_sync();
-          if (ln == 0) dtile[k][k] = lkk;
-          if (ln > k && ln < 16)
-            for (int c = k + 1; c <= ln; ++c) dtile[ln][c] -= dtile[ln][k] * dtile[c][k];
-          wave_sync();
+          if (r == k) mypiv = real ? dk : T(1);
+          x[k] = r > k ? (real ? x[k] / lkk : T(0)) : (r == k ? lkk : x[k]);
+#pragma unroll
+          for (int c = k + 1; c < 16; ++c) {
+            const T lck = lane_read(x[k], c);
+            if (r >= c) x[c] -= x[k] * lck;
+          }
+        }
+        if (ln < 16) {
+#pragma unroll
+          for (int c = 0; c < 16; ++c) dtile[r][c] = c <= r ? x[c] : T(0);
         }
       }
       __syncthreads();
       // rows of the panel: L_IJ = C_IJ L_JJ^-T (rows below the tile), L_JJ in the tile
       for (int i = J * 16 + tid; i < P; i += 256) {
+        // the factor tile is re-read from LDS per row rather than held in
+        // 136 registers across the loop
+        asm volatile("" ::: "memory");
         T x[16];
         if (i < J * 16 + 16) {
 #pragma unroll
@@ -177,22 +229,29 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
       }
       __threadfence_block();
       __syncthreads();
-      if (tid == 0) {
-        for (int c = 0; c < 16; ++c) {
-          const int k = J * 16 + c;
-          if (k < p) {
-            const double dd = (double)piv[c];
-            if (!(dd > guard)) flag |= a.fp32_guard ? 1 : 2;
-            if (!(dd > 0.0)) flag |= 2;
-            if (k >= m) {
-              const double wk = (double)M[(size_t)k * ld + p];
-              acc_ll += log(dd) + wk * wk;
-              qb += wk * wk;
-            }
+      // pivot k = 16 J + tid of the panel: lanes 0..15 of wave 0 keep running sums
+      if (tid < 16) {
+        const int k = J * 16 + tid;
+        if (k < p) {
+          const double dd = (double)mypiv;
+          if (!(dd > guard)) flag |= a.fp32_guard ? 1 : 2;
+          if (!(dd > 0.0)) flag |= 2;
+          if (k >= m) {
+            const double wk = (double)M[(size_t)k * ld + p];
+            acc_ll += log(dd) + wk * wk;
+            qb += wk * wk;
           }
         }
       }
       __syncthreads();
+    }
+    if (wv == 0) {
+#pragma unroll
+      for (int off = 8; off > 0; off >>= 1) {
+        acc_ll += __shfl_xor(acc_ll, off);
+        qb += __shfl_xor(qb, off);
+        flag |= __shfl_xor(flag, off);
+      }
     }
     const size_t o = (size_t)tt * a.bc + b;
     if (tid == 0) {
@@ -224,6 +283,7 @@ __global__ void __launch_bounds__(256) bv_large_kernel(LargeArgs a, ThetaPack th
         __syncthreads();
         // X_K <- L_KK^-T X_K, one column per thread (back-substitution)
         for (int c = tid; c < NRP; c += 256) {
+          asm volatile("" ::: "memory");   // re-read the tile from LDS per column
           T x[16];
 #pragma unroll
           for (int r = 0; r < 16; ++r) x[r] = X[(size_t)c * ld + K * 16 + r];

@@ -133,6 +133,8 @@ struct LargeArgs {
   double* gpart;         // gradient launches: [(theta * bc + block) * 3 + k]
 };
 constexpr int kLargeCfg = 31;   // size class of blocks above the register capacity
+// bytes of large-block slots above which a plan factors no more than 256 blocks at a time
+constexpr size_t kLargeSlotCap = (size_t)4 << 30;
 // elements of one large-block slot: the P x P matrix, the gradient's P x 16 ceil((l + 2) / 16)
 // right-hand sides and 3 P staged coordinates, P = 16 ceil((p_max + 1) / 16)
 size_t large_slot_elems(int pmax, int lmax);
