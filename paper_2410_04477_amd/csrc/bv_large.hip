@@ -68,11 +68,9 @@ template <> __device__ __forceinline__ double lane_read<double>(double v, int la
 #ifndef BV_LARGE_WAVES
 #define BV_LARGE_WAVES 6
 #endif
-#ifndef BV_LARGE_UNROLL
-#define BV_LARGE_UNROLL 2   // panel-update steps whose operand loads are issued together
+#ifndef BV_LARGE_DEPTH
+#define BV_LARGE_DEPTH 2    // panel-update steps whose operand loads are issued together
 #endif
-#define BV_PRAGMA(x) _Pragma(#x)
-#define BV_UNROLL(n) BV_PRAGMA(unroll n)
 template <typename T, bool GRAD>
 __global__ void __launch_bounds__(256, BV_LARGE_WAVES) bv_large_kernel(LargeArgs a, ThetaPack thp) {
   typedef typename LMma<T>::acc acc_t;
@@ -165,15 +163,27 @@ __global__ void __launch_bounds__(256, BV_LARGE_WAVES) bv_large_kernel(LargeArgs
         acc_t c;
 #pragma unroll
         for (int r = 0; r < 4; ++r) c[r] = M[(size_t)(J * 16 + lr) * ld + I * 16 + LMma<T>::row(lg, r)];
-        BV_UNROLL(BV_LARGE_UNROLL)
-        for (int K = 0; K < J; ++K) {
+        // BV_LARGE_DEPTH steps of operands are loaded before their products, so
+        // that 8 BV_LARGE_DEPTH loads are in flight; the steps past J - 1 of the
+        // last group re-load step J - 1 and multiply by zero (no branch, so the
+        // loads stay in one scheduling region)
+        for (int K0 = 0; K0 < J; K0 += BV_LARGE_DEPTH) {
+          T av[BV_LARGE_DEPTH][4], bv[BV_LARGE_DEPTH][4];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const int col = K * 16 + 4 * s + lg;
-            const T av = -M[(size_t)col * ld + I * 16 + lr];
-            const T bv = M[(size_t)col * ld + J * 16 + lr];
-            c = LMma<T>::op(av, bv, c);
+          for (int d = 0; d < BV_LARGE_DEPTH; ++d) {
+            const int K = K0 + d < J ? K0 + d : J - 1;
+            const T sg = K0 + d < J ? T(-1) : T(0);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+              const int col = K * 16 + 4 * s + lg;
+              av[d][s] = sg * M[(size_t)col * ld + I * 16 + lr];
+              bv[d][s] = M[(size_t)col * ld + J * 16 + lr];
+            }
           }
+#pragma unroll
+          for (int d = 0; d < BV_LARGE_DEPTH; ++d)
+#pragma unroll
+            for (int s = 0; s < 4; ++s) c = LMma<T>::op(av[d][s], bv[d][s], c);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) M[(size_t)(J * 16 + lr) * ld + I * 16 + LMma<T>::row(lg, r)] = c[r];
