@@ -2,7 +2,6 @@
 bit, and the ordering study of Section 3 in small: KL divergences (eq.
 (kl-gaussian-vecchia)) of random, Morton, Hilbert, KD-tree and maxmin
 orders, GPU against the oracle."""
-import time
 
 import numpy as np
 import pytest
@@ -110,31 +109,23 @@ def test_kl_trends_16k():
             cache[th] = float(api.loglik(ex_plan, sl, zero, _t(np.zeros(1), torch.int32), [th])[0][0])
         return cache[th]
 
-    def timed_loglik(plan, lp, nid, th, reps=5):
-        """l(theta; 0) and the mean time of one evaluation (FP64, after a warm-up)."""
-        v = float(api.loglik(plan, lp, zero, nid, [th])[0][0])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(reps):
-            api.loglik(plan, lp, zero, nid, [th])
-        torch.cuda.synchronize()
-        return v, (time.perf_counter() - t0) / reps
+    def loglik0(plan, lp, nid, th):
+        """l(theta; 0), FP64."""
+        return float(api.loglik(plan, lp, zero, nid, [th])[0][0])
 
-    def bv(th, bc, m, seed, with_time=False):
+    def bv(th, bc, m, seed):
         perm, bp, _ = api.blocks(sl, bc, torch.tensor(W.kmeans_init(n, bc, seed), device=DEV),
                                  torch.tensor(W.block_permutation(bc, seed), device=DEV), [1.0, 1.0], 10)
         lp = api.permute_rows(sl, perm)
         npt, nid = api.neighbors(lp, bp, m, [1.0, 1.0])
-        v, dt = timed_loglik(api.Plan(bp, npt, n, 1), lp, nid, th)
-        return (v, dt) if with_time else v
+        return loglik0(api.Plan(bp, npt, n, 1), lp, nid, th)
 
-    def cv(th, m, seed, with_time=False):
+    def cv(th, m, seed):
         order = torch.tensor(W.point_permutation(n, seed), device=DEV)
         lp = api.permute_rows(sl, order)
         bp = _t(np.arange(n + 1), torch.int32)
         npt, nid = api.neighbors(lp, bp, m, [1.0, 1.0])
-        v, dt = timed_loglik(api.Plan(bp, npt, n, 1), lp, nid, th)
-        return (v, dt) if with_time else v
+        return loglik0(api.Plan(bp, npt, n, 1), lp, nid, th)
 
     th = W.Theta(1.0, 0.052537, 0.0, 1.5)
     ex = exact(th)
@@ -158,12 +149,3 @@ def test_kl_trends_16k():
     growth_cv = rows[2.5][1] / max(rows[0.5][1], 1e-12)
     print(f"KL growth nu 0.5 -> 2.5: BV {growth_bv:.2f}x, CV {growth_cv:.2f}x")
     assert growth_cv > growth_bv
-
-    # accuracy against time per FP64 evaluation (the paper's time-to-solution
-    # comparison), nu = 1.5: printed, not asserted
-    e = exact(th)
-    for m in (30, 60, 150):
-        vb, tb = bv(th, 1500, m, 2400, with_time=True)
-        vc, tc = cv(th, m, 2500, with_time=True)
-        assert e - vb >= 0 and e - vc >= 0
-        print(f"m={m}: BV-1500 KL {e - vb:.3e} in {tb * 1e3:.2f} ms; CV-16K KL {e - vc:.3e} in {tc * 1e3:.2f} ms")
