@@ -63,16 +63,26 @@ template <> __device__ __forceinline__ double lane_read<double>(double v, int la
 // the bordered matrix, column-major lower part, P x P; in gradient launches
 // the right-hand sides X (P rows, 16 ceil((l + 2) / 16) columns, column-major)
 // follow it; then the scaled coordinates of the p points (3 x P).
-// at least 6 waves per SIMD (80 VGPRs): 6 workgroups of 4 waves per compute
-// unit, so that up to 1536 blocks are in flight and hide each other's latency
-#ifndef BV_LARGE_WAVES
-#define BV_LARGE_WAVES 6
+// Waves per SIMD at least: FP32 6 (80 VGPRs, 6 workgroups of 4 waves per
+// compute unit, up to 1536 blocks in flight hiding each other's latency);
+// FP64 4 (128 VGPRs), which holds two output tiles per wave in the panel
+// update (each load of the panel operand feeds two products)
+#ifndef BV_LARGE_WAVES32
+#define BV_LARGE_WAVES32 6
+#endif
+#ifndef BV_LARGE_WAVES64
+#define BV_LARGE_WAVES64 4
+#endif
+#ifndef BV_LARGE_TPW64
+#define BV_LARGE_TPW64 2    // FP64 output tiles per wave in one pass of the panel update
 #endif
 #ifndef BV_LARGE_DEPTH
 #define BV_LARGE_DEPTH 2    // panel-update steps whose operand loads are issued together
 #endif
 template <typename T, bool GRAD>
-__global__ void __launch_bounds__(256, BV_LARGE_WAVES) bv_large_kernel(LargeArgs a, ThetaPack thp) {
+__global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LARGE_WAVES32)
+    bv_large_kernel(LargeArgs a, ThetaPack thp) {
+  constexpr int TPW = sizeof(T) == 8 ? BV_LARGE_TPW64 : 1;
   typedef typename LMma<T>::acc acc_t;
   __shared__ T dtile[16][17];
   __shared__ T colc[4][256];   // generation: coordinates and y of 256 columns
@@ -159,34 +169,81 @@ __global__ void __launch_bounds__(256, BV_LARGE_WAVES) bv_large_kernel(LargeArgs
     const int Gp = (p + 15) >> 4;  // panels holding real columns
     for (int J = 0; J < Gp; ++J) {
       // panel update C_IJ = A_IJ - sum_{K<J} L_IK L_JK^T, output tiles I >= J dealt to waves
-      for (int I = J + wv; I < G; I += 4) {
-        acc_t c;
+      if constexpr (TPW == 1) {
+        for (int I = J + wv; I < G; I += 4) {
+          acc_t c;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) c[r] = M[(size_t)(J * 16 + lr) * ld + I * 16 + LMma<T>::row(lg, r)];
-        // BV_LARGE_DEPTH steps of operands are loaded before their products, so
-        // that 8 BV_LARGE_DEPTH loads are in flight; the steps past J - 1 of the
-        // last group re-load step J - 1 and multiply by zero (no branch, so the
-        // loads stay in one scheduling region)
-        for (int K0 = 0; K0 < J; K0 += BV_LARGE_DEPTH) {
-          T av[BV_LARGE_DEPTH][4], bv[BV_LARGE_DEPTH][4];
+          for (int r = 0; r < 4; ++r) c[r] = M[(size_t)(J * 16 + lr) * ld + I * 16 + LMma<T>::row(lg, r)];
+          // BV_LARGE_DEPTH steps of operands are loaded before their products, so
+          // that 8 BV_LARGE_DEPTH loads are in flight; the steps past J - 1 of the
+          // last group re-load step J - 1 and multiply by zero (no branch, so the
+          // loads stay in one scheduling region)
+          for (int K0 = 0; K0 < J; K0 += BV_LARGE_DEPTH) {
+            T av[BV_LARGE_DEPTH][4], bv[BV_LARGE_DEPTH][4];
 #pragma unroll
-          for (int d = 0; d < BV_LARGE_DEPTH; ++d) {
-            const int K = K0 + d < J ? K0 + d : J - 1;
-            const T sg = K0 + d < J ? T(-1) : T(0);
+            for (int d = 0; d < BV_LARGE_DEPTH; ++d) {
+              const int K = K0 + d < J ? K0 + d : J - 1;
+              const T sg = K0 + d < J ? T(-1) : T(0);
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-              const int col = K * 16 + 4 * s + lg;
-              av[d][s] = sg * M[(size_t)col * ld + I * 16 + lr];
-              bv[d][s] = M[(size_t)col * ld + J * 16 + lr];
+              for (int s = 0; s < 4; ++s) {
+                const int col = K * 16 + 4 * s + lg;
+                av[d][s] = sg * M[(size_t)col * ld + I * 16 + lr];
+                bv[d][s] = M[(size_t)col * ld + J * 16 + lr];
+              }
             }
+#pragma unroll
+            for (int d = 0; d < BV_LARGE_DEPTH; ++d)
+#pragma unroll
+              for (int s = 0; s < 4; ++s) c = LMma<T>::op(av[d][s], bv[d][s], c);
           }
 #pragma unroll
-          for (int d = 0; d < BV_LARGE_DEPTH; ++d)
-#pragma unroll
-            for (int s = 0; s < 4; ++s) c = LMma<T>::op(av[d][s], bv[d][s], c);
+          for (int r = 0; r < 4; ++r) M[(size_t)(J * 16 + lr) * ld + I * 16 + LMma<T>::row(lg, r)] = c[r];
         }
+      } else {
+        // TPW output tiles I0, I0 + 4, ... per wave share each load of
+        // the panel operand; BV_LARGE_DEPTH steps of operands are loaded before
+        // their products.  Steps past J - 1 of the last group re-load step J - 1
+        // and tiles past G - 1 re-load tile I0, both multiplied by zero (no
+        // branch, so the loads stay in one scheduling region)
+        for (int I0 = J + wv; I0 < G; I0 += 4 * TPW) {
+          acc_t c[TPW];
+          int It[TPW];
+          T tz[TPW];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) M[(size_t)(J * 16 + lr) * ld + I * 16 + LMma<T>::row(lg, r)] = c[r];
+          for (int t = 0; t < TPW; ++t) {
+            It[t] = I0 + 4 * t < G ? I0 + 4 * t : I0;
+            tz[t] = I0 + 4 * t < G ? T(-1) : T(0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) c[t][r] = M[(size_t)(J * 16 + lr) * ld + It[t] * 16 + LMma<T>::row(lg, r)];
+          }
+          for (int K0 = 0; K0 < J; K0 += BV_LARGE_DEPTH) {
+            T av[BV_LARGE_DEPTH][TPW][4], bv[BV_LARGE_DEPTH][4];
+#pragma unroll
+            for (int d = 0; d < BV_LARGE_DEPTH; ++d) {
+              const int K = K0 + d < J ? K0 + d : J - 1;
+              const T sg = K0 + d < J ? T(1) : T(0);
+#pragma unroll
+              for (int s = 0; s < 4; ++s) {
+                const int col = K * 16 + 4 * s + lg;
+                bv[d][s] = M[(size_t)col * ld + J * 16 + lr];
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) av[d][t][s] = (sg * tz[t]) * M[(size_t)col * ld + It[t] * 16 + lr];
+              }
+            }
+#pragma unroll
+            for (int d = 0; d < BV_LARGE_DEPTH; ++d)
+#pragma unroll
+              for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int t = 0; t < TPW; ++t) c[t] = LMma<T>::op(av[d][t][s], bv[d][s], c[t]);
+          }
+#pragma unroll
+          for (int t = 0; t < TPW; ++t)
+            if (I0 + 4 * t < G) {
+#pragma unroll
+              for (int r = 0; r < 4; ++r) M[(size_t)(J * 16 + lr) * ld + It[t] * 16 + LMma<T>::row(lg, r)] = c[t][r];
+            }
+        }
       }
       __threadfence_block();
       __syncthreads();
