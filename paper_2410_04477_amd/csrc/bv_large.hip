@@ -191,6 +191,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LA
                 bv[d][s] = M[(size_t)col * ld + J * 16 + lr];
               }
             }
+            // all loads of the group issue before the first product (left to
+            // itself the scheduler interleaves FP32 loads with the products)
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int d = 0; d < BV_LARGE_DEPTH; ++d)
 #pragma unroll
@@ -230,6 +233,9 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LA
                 for (int t = 0; t < TPW; ++t) av[d][t][s] = (sg * tz[t]) * M[(size_t)col * ld + It[t] * 16 + lr];
               }
             }
+            // all loads of the group issue before the first product (left to
+            // itself the scheduler interleaves FP32 loads with the products)
+            __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int d = 0; d < BV_LARGE_DEPTH; ++d)
 #pragma unroll
