@@ -76,13 +76,17 @@ template <> __device__ __forceinline__ double lane_read<double>(double v, int la
 #ifndef BV_LARGE_TPW64
 #define BV_LARGE_TPW64 2    // FP64 output tiles per wave in one pass of the panel update
 #endif
-#ifndef BV_LARGE_DEPTH
-#define BV_LARGE_DEPTH 2    // panel-update steps whose operand loads are issued together
+#ifndef BV_LARGE_DEPTH32
+#define BV_LARGE_DEPTH32 2  // panel-update steps whose operand loads are issued together
+#endif
+#ifndef BV_LARGE_DEPTH64
+#define BV_LARGE_DEPTH64 2
 #endif
 template <typename T, bool GRAD>
 __global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LARGE_WAVES32)
     bv_large_kernel(LargeArgs a, ThetaPack thp) {
   constexpr int TPW = sizeof(T) == 8 ? BV_LARGE_TPW64 : 1;
+  constexpr int DEPTH = sizeof(T) == 8 ? BV_LARGE_DEPTH64 : BV_LARGE_DEPTH32;
   typedef typename LMma<T>::acc acc_t;
   __shared__ T dtile[16][17];
   __shared__ T colc[4][256];   // generation: coordinates and y of 256 columns
@@ -174,14 +178,14 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LA
           acc_t c;
 #pragma unroll
           for (int r = 0; r < 4; ++r) c[r] = M[(size_t)(J * 16 + lr) * ld + I * 16 + LMma<T>::row(lg, r)];
-          // BV_LARGE_DEPTH steps of operands are loaded before their products, so
-          // that 8 BV_LARGE_DEPTH loads are in flight; the steps past J - 1 of the
+          // DEPTH steps of operands are loaded before their products, so
+          // that 8 DEPTH loads are in flight; the steps past J - 1 of the
           // last group re-load step J - 1 and multiply by zero (no branch, so the
           // loads stay in one scheduling region)
-          for (int K0 = 0; K0 < J; K0 += BV_LARGE_DEPTH) {
-            T av[BV_LARGE_DEPTH][4], bv[BV_LARGE_DEPTH][4];
+          for (int K0 = 0; K0 < J; K0 += DEPTH) {
+            T av[DEPTH][4], bv[DEPTH][4];
 #pragma unroll
-            for (int d = 0; d < BV_LARGE_DEPTH; ++d) {
+            for (int d = 0; d < DEPTH; ++d) {
               const int K = K0 + d < J ? K0 + d : J - 1;
               const T sg = K0 + d < J ? T(-1) : T(0);
 #pragma unroll
@@ -195,7 +199,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LA
             // itself the scheduler interleaves FP32 loads with the products)
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int d = 0; d < BV_LARGE_DEPTH; ++d)
+            for (int d = 0; d < DEPTH; ++d)
 #pragma unroll
               for (int s = 0; s < 4; ++s) c = LMma<T>::op(av[d][s], bv[d][s], c);
           }
@@ -204,7 +208,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LA
         }
       } else {
         // TPW output tiles I0, I0 + 4, ... per wave share each load of
-        // the panel operand; BV_LARGE_DEPTH steps of operands are loaded before
+        // the panel operand; DEPTH steps of operands are loaded before
         // their products.  Steps past J - 1 of the last group re-load step J - 1
         // and tiles past G - 1 re-load tile I0, both multiplied by zero (no
         // branch, so the loads stay in one scheduling region)
@@ -219,10 +223,10 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LA
 #pragma unroll
             for (int r = 0; r < 4; ++r) c[t][r] = M[(size_t)(J * 16 + lr) * ld + It[t] * 16 + LMma<T>::row(lg, r)];
           }
-          for (int K0 = 0; K0 < J; K0 += BV_LARGE_DEPTH) {
-            T av[BV_LARGE_DEPTH][TPW][4], bv[BV_LARGE_DEPTH][4];
+          for (int K0 = 0; K0 < J; K0 += DEPTH) {
+            T av[DEPTH][TPW][4], bv[DEPTH][4];
 #pragma unroll
-            for (int d = 0; d < BV_LARGE_DEPTH; ++d) {
+            for (int d = 0; d < DEPTH; ++d) {
               const int K = K0 + d < J ? K0 + d : J - 1;
               const T sg = K0 + d < J ? T(1) : T(0);
 #pragma unroll
@@ -237,7 +241,7 @@ __global__ void __launch_bounds__(256, sizeof(T) == 8 ? BV_LARGE_WAVES64 : BV_LA
             // itself the scheduler interleaves FP32 loads with the products)
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int d = 0; d < BV_LARGE_DEPTH; ++d)
+            for (int d = 0; d < DEPTH; ++d)
 #pragma unroll
               for (int s = 0; s < 4; ++s)
 #pragma unroll
